@@ -1,0 +1,84 @@
+"""The five measured workloads, as seeded recipes.
+
+  er2k      ER n=2,000 m=20,000, weighted cascade, |S|=1 (out-degree >= 1),
+            100,000 fixed-count samples, query id 0; plus the 16-node/24-edge
+            enumeration graph.
+  cl1m      Chung-Lu n=1e6, m~1e7, exponent 2.1, trivalency p, |S|=1,
+            estimate to eps=0.05, delta=1/n.
+  cl4m      Chung-Lu n=4e6, m~7e7, exponent 2.1, weighted cascade, 4,096 seed
+            sets |S| in [1,1000] (half uniform, half top-1% out-degree),
+            eps=0.1, delta=1e-3.
+  cl1m_sig  Chung-Lu n=1e6, m~1e7, p = sigmoid(theta), theta ~ N(-3,1),
+            |S|=50, 1e6 fixed-count samples, forward + backward.
+  cl100m    Chung-Lu n=1e8, m~1.5e9, weighted cascade, 256 seed sets with
+            |S| in {1,10,100}, eps=0.05, delta=1e-6.
+
+Seeds: graph seed = workload number (1..5; the 16-node graph uses 16),
+probability seed = 200 + number, seed-set seed = 100 + number, theta seed 40.
+The Philox run seed used by tests and the bench is RUN_SEED.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import graphs as G
+
+RUN_SEED = 0x17044794
+
+CONFIGS = {
+    "er2k": dict(number=1, n=2000, m=20000, model="wc", samples=100_000),
+    "cl1m": dict(number=2, n=1_000_000, m=10_000_000, gamma=2.1, model="trivalency",
+                 eps=0.05, delta=1e-6),
+    "cl4m": dict(number=3, n=4_000_000, m=70_000_000, gamma=2.1, model="wc",
+                 eps=0.1, delta=1e-3, queries=4096, kmin=1, kmax=1000),
+    "cl1m_sig": dict(number=4, n=1_000_000, m=10_000_000, gamma=2.1, model="sigmoid",
+                     k=50, samples=1_000_000),
+    "cl100m": dict(number=5, n=100_000_000, m=1_500_000_000, gamma=2.1, model="wc",
+                   eps=0.05, delta=1e-6, queries=256, sizes=(1, 10, 100)),
+}
+
+
+def _probs(g, model, number):
+    if model == "wc":
+        return G.wc_probs(g), None
+    if model == "trivalency":
+        return G.trivalency_probs(g, 200 + number), None
+    if model == "sigmoid":
+        theta, p = G.sigmoid_theta_probs(g, 40)
+        return p, theta
+    raise ValueError(model)
+
+
+def make_config(name: str, n: int | None = None, m: int | None = None):
+    """Build (graph, seed_sets, extra) for a workload.  `n`/`m` override the
+    size (for scaled-down parity cases with the same recipe).
+
+    seed_sets is a list of int32 arrays.  extra holds theta where relevant and
+    the eps/delta/sample counts of the workload."""
+    c = dict(CONFIGS[name])
+    num = c["number"]
+    nn = c["n"] if n is None else n
+    mm = c["m"] if m is None else m
+    extra = dict(c)
+    if name == "er2k":
+        g = G.er_graph(nn, mm, num)
+    else:
+        g = G.chung_lu_graph(nn, mm, c["gamma"], num)
+    p, theta = _probs(g, c["model"], num)
+    g = g.with_p(p)
+    extra["theta"] = theta
+    if name in ("er2k", "cl1m"):
+        sets = [G.seed_node_outdeg_ge1(g, 100 + num)]
+    elif name == "cl1m_sig":
+        sets = [G.uniform_seed_set(g, c["k"], 100 + num)]
+    elif name == "cl4m":
+        off, seeds = G.batched_seed_sets(g, c["queries"], c["kmin"], c["kmax"], 100 + num)
+        sets = [seeds[off[i]:off[i + 1]] for i in range(c["queries"])]
+    elif name == "cl100m":
+        rng = np.random.Generator(np.random.PCG64(100 + num))
+        sizes = np.array(c["sizes"])[np.arange(c["queries"]) % len(c["sizes"])]
+        sets = [np.sort(rng.choice(g.n, size=int(k), replace=False)).astype(np.int32)
+                for k in sizes]
+    else:
+        raise ValueError(name)
+    return g, sets, extra
