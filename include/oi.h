@@ -1,0 +1,188 @@
+/*
+ * oi.h -- C ABI of the MI355X (gfx950) outward-influence estimator.
+ *
+ * Implements, on one GPU, the data-parallel hot path of SOIEA / SIEA from
+ * Nguyen, Dinh, Thai, "Outward Influence and Cascade Size Estimation in
+ * Billion-scale Networks": Importance IC Polling samples (Sec. 3.1, Alg. 1)
+ * under the Independent Cascade model (Sec. 2.1), driven by the RSA stopping
+ * rule (Sec. 4, Algs. 2 and 3), for one seed set (Alg. 4 / Alg. 5) or many,
+ * plus a score-function backward of the fixed-count estimate.
+ *
+ * Conventions for every call:
+ *   - Every function returns oi_status; OI_OK = 0.  On failure
+ *     oi_last_error() returns a message for the calling thread.  No
+ *     exception crosses this boundary.
+ *   - "host" pointers are CPU memory, "device" pointers are memory of the
+ *     GPU the graph lives on.  Inputs are only read and stay owned by the
+ *     caller; the library copies what it keeps.  Outputs go to caller-owned
+ *     buffers of the stated size.
+ *   - All GPU work of a graph is issued on the HIP stream given at creation
+ *     (or oi_set_stream); every call returns after that work has completed.
+ *     Calls on one graph are not thread-safe; distinct graphs are.
+ *   - Samples are keyed, not scheduled: the i-th sample of a stream of a
+ *     query is a pure function of (graph, seed set, query_id, run_seed,
+ *     stream, i).  Randomness is Philox4x32-10 with key (query_id, run_seed)
+ *     and counter (lo32(idx), hi32(idx), lo32(i), kind<<28 | stream<<27 |
+ *     hi32(i)); the coin of CSR edge e is word e%4 of the block with
+ *     idx = e/4, kind 0, and is live iff word < floor(p_e * 2^32); Stage-1
+ *     entry j uses kind 2 the same way with floor(P_{S,v_j} * 2^32); the
+ *     selection uniform is kind 1, idx 0, U = ((w0>>5)*2^26 + (w1>>6))*2^-53.
+ */
+#ifndef OI_H
+#define OI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct oi_graph oi_graph;
+
+typedef enum {
+  OI_OK = 0,
+  OI_EINVAL = -1, /* invalid argument (sizes, ranges, null pointers) */
+  OI_ERANGE = -2, /* value outside the supported range (ids, sample counts) */
+  OI_ENOMEM = -3, /* device or host allocation failed */
+  OI_EHIP = -4,   /* a HIP runtime call failed */
+  OI_ESTATE = -5  /* internal consistency check failed (reported by a kernel) */
+} oi_status;
+
+/* SOIEA estimates OI(S) with X = Y (Alg. 4); SIEA estimates IS(S) with
+ * X = Z = beta_0 * Y + |S| (Eq. z_s, Alg. 5).  Both report OI and IS. */
+typedef enum { OI_MODE_SOIEA = 0, OI_MODE_SIEA = 1 } oi_mode;
+
+/* Gradient with respect to p_e, or to theta_e where p_e = sigmoid(theta_e). */
+typedef enum { OI_PARAM_P = 0, OI_PARAM_THETA = 1 } oi_param;
+
+typedef struct {
+  double oi;          /* estimate of the outward influence OI(S) = I(S) - |S| */
+  double is;          /* estimate of the influence spread IS(S) = OI(S) + |S| */
+  double beta0;       /* probability of a non-trivial cascade (Eq. zerop) */
+  double mu;          /* estimate of E[X] returned by RSA (or GSRA) */
+  double mu1;         /* step-1 rough estimate of RSA */
+  uint64_t T1, h1;    /* step 1: samples until the stopping rule, and their sum of Y */
+  uint64_t nsigma;    /* step 2: number of pairs of X' */
+  uint64_t D_lo, D_hi;/* step 2: 128-bit sum of squared paired differences of Y' */
+  uint64_t T, hT;     /* step 3: samples used for the estimate, and their sum of Y */
+  uint64_t samples_x, samples_xp; /* samples generated on the X and X' streams */
+  uint64_t sum_y;     /* sum of Y over all generated samples */
+  uint64_t edges_examined; /* sum over generated samples of (Stage-1 entries after
+                              the selected one) + (out-degree of every activated node) */
+  int64_t k;          /* |S| after removing duplicate seeds */
+  int64_t l;          /* |N^out_S|, the size of the Stage-1 table */
+  int32_t gsra_only;  /* 1 if eps >= 1/4 (RSA reduces to GSRA, Alg. 3 lines 1-2) */
+  int32_t early;      /* 1 if the first GSRA returned its lower bound without sampling */
+  int32_t status;     /* per-query oi_status (batch calls) */
+  int32_t rounds;     /* sampling launches used */
+} oi_result;
+
+/*
+ * Create a graph.  CSR: row_ptr[n+1] (int64, row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = m), col[m] (int32 targets in [0, n)), p[m] (fp32 IC
+ * probabilities in [0, 1], Sec. 2.1: edge (u, v) is live with probability
+ * w(u, v)).  Edge ids are CSR positions.  If device_ptrs is nonzero the three
+ * arrays are device pointers, else host pointers.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Limits: n < 2^31, out-degree < 2^29.
+ * Errors: OI_EINVAL for malformed CSR or p outside [0, 1] (NaN included).
+ */
+oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const float* p,
+                          int device_ptrs, void* hip_stream, oi_graph** out);
+
+/* Replace all m edge probabilities (same topology).  p as in oi_graph_create. */
+oi_status oi_graph_set_probs(oi_graph* g, const float* p, int device_ptr);
+
+/* Change the HIP stream used for the graph's work. */
+oi_status oi_set_stream(oi_graph* g, void* hip_stream);
+
+void oi_graph_destroy(oi_graph* g);
+
+/*
+ * Stage-1 table of a seed set (Sec. 3.1): N^out_S sorted by node id, P_{S,v}
+ * (Eq. psv, product over the edges from S into v in ascending edge id),
+ * CDF_j = sum_{i<=j} Pr[A_i] (Eq. pai) and beta_0 = CDF_l (Eq. zerop), as the
+ * sampler uses them.  seeds: host int32[k]; duplicates are removed.  Outputs
+ * (host, any may be NULL, filled only if l <= cap): v[l], P[l], cdf[l+1]
+ * (cdf[0] = 0), thr[l] = floor(P * 2^32).  *l_out and *beta0 always set.
+ */
+oi_status oi_stage1_table(oi_graph* g, const int32_t* seeds, int64_t k, int64_t cap, int64_t* l_out,
+                          double* beta0, int32_t* v, double* P, double* cdf, uint64_t* thr);
+
+/*
+ * Fixed-count IICP sampling (Alg. 1): samples first .. first+count-1 of
+ * stream `stream` (0 = X, 1 = X') of the query (query_id, seeds).
+ * y_out: device uint32[count] (or NULL) receives Y per sample;
+ * e_out: device uint64[count] (or NULL) receives the examined-edge count per
+ * sample.  sums (host, may be NULL): sum_y, edges_examined, beta0, k, l.
+ * If beta_0 = 0 nothing is sampled and y_out is left untouched.
+ */
+oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
+                          uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out,
+                          oi_result* sums);
+
+/*
+ * (eps, delta)-estimate of OI(S) and IS(S) = OI(S) + |S| (Sec. 2, estimation
+ * problems) by SOIEA (Alg. 4) or SIEA (Alg. 5) with RSA (Alg. 3).
+ * Requires 0 < eps < 1 and 0 < delta < 1/2.  beta_0 = 0 gives OI = 0,
+ * IS = |S| without sampling.  out: host oi_result.
+ */
+oi_status oi_estimate(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, double eps, double delta,
+                      oi_mode mode, uint32_t run_seed, oi_result* out);
+
+/*
+ * Many seed sets at once: set q is seeds[seed_off[q] .. seed_off[q+1]) with
+ * query id query_ids[q] (host arrays; seed_off has nq+1 entries).  Every set
+ * keeps its own RSA state; each sampling round serves all unfinished sets in
+ * one launch.  Per-set results are identical to oi_estimate with the same
+ * query id.  out: host oi_result[nq]; out[q].status holds the set's status.
+ */
+oi_status oi_estimate_batch(oi_graph* g, int32_t nq, const int64_t* seed_off, const int32_t* seeds,
+                            const uint32_t* query_ids, double eps, double delta, oi_mode mode,
+                            uint32_t run_seed, oi_result* out);
+
+/*
+ * Score-function gradient of the fixed-count estimate beta_0 * mean(Y) of
+ * OI(S) over samples first .. first+count-1 of stream X, with respect to
+ * every edge probability (OI_PARAM_P) or to theta with p = sigmoid(theta)
+ * (OI_PARAM_THETA), multiplied by grad_scale.  Each sample is recomputed from
+ * its Philox key; y_in (device uint32[count], the forward's Y) may be NULL,
+ * in which case the forward is run first.  Accumulation is exact (64-bit
+ * integer sums of Y per edge and outcome), finished in fp64 and written as
+ * fp32 to grad_out (device float[m]; every entry is written).  The
+ * estimator is unbiased for edges with 0 < p_e < 1.
+ */
+oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, uint64_t first,
+                      uint64_t count, uint32_t run_seed, const uint32_t* y_in, oi_param param, double grad_scale,
+                      float* grad_out);
+
+/* Kernel timing collected with HIP events on the graph's stream. */
+typedef struct {
+  double small_ms;      /* total time of the small-cascade sampling kernel */
+  double large_ms;      /* total time of the large-cascade sampling kernel */
+  double other_ms;      /* reductions and backward finishing kernels */
+  uint64_t small_launches, large_launches;
+  uint64_t samples;     /* samples produced by sampling launches */
+  uint64_t deferred;    /* samples handed from the small to the large kernel */
+  uint64_t sum_y;       /* activated nodes (sum of Y) */
+  uint64_t edges;       /* examined edges (as in oi_result.edges_examined) */
+  uint64_t large_sum_y; /* the part of sum_y produced by the large-cascade kernel */
+  uint64_t large_edges; /* the part of edges examined by the large-cascade kernel */
+} oi_timing;
+
+/* enable != 0 turns event timing on (and resets the counters). */
+oi_status oi_timing_enable(oi_graph* g, int enable);
+oi_status oi_timing_get(oi_graph* g, oi_timing* out);
+
+/* Tuning of the small-cascade kernel: variant index (see oi_variant_info) and
+ * samples taken per work-counter increment.  Values <= 0 keep the current one. */
+oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int64_t round_max);
+int oi_num_variants(void);
+oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* ring_cap, int* rounds_per_pass);
+
+const char* oi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* OI_H */

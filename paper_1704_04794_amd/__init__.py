@@ -1,0 +1,96 @@
+"""MI355X (gfx950) outward-influence estimation: IICP sampling driven by RSA.
+
+The computation lives in liboi_hip.so (HIP kernels + C ABI, include/oi.h);
+this package is its binding.  `Graph` owns a library graph handle; the
+module-level `oi_*` functions are the C entry points one to one.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from ._binding import (  # noqa: F401
+    LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_backward,
+    oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_set_probs, oi_last_error,
+    oi_num_variants, oi_sample_fixed, oi_set_stream, oi_set_tuning, oi_stage1_table, oi_timing_enable,
+    oi_timing_get, oi_variant_info)
+
+RUN_SEED = 0x17044794
+
+
+def _is_device_tensor(x) -> bool:
+    return hasattr(x, "is_cuda") and bool(x.is_cuda)
+
+
+class Graph:
+    """A CSR graph with fp32 IC edge probabilities resident on the GPU.
+
+    row_ptr int64[n+1], col int32[m], p float32[m]: numpy arrays (host) or
+    torch CUDA tensors (device)."""
+
+    def __init__(self, n, row_ptr, col, p, stream=None):
+        dev = _is_device_tensor(row_ptr)
+        if dev:
+            row_ptr, col, p = row_ptr.contiguous(), col.contiguous(), p.contiguous()
+        else:
+            row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+            col = np.ascontiguousarray(col, dtype=np.int32)
+            p = np.ascontiguousarray(p, dtype=np.float32)
+        self.n = int(n)
+        self.m = int(col.shape[0])
+        self.h = oi_graph_create(self.n, self.m, row_ptr, col, p, 1 if dev else 0, stream)
+
+    @classmethod
+    def from_inputs(cls, g, stream=None):
+        """From an object with n, row_ptr, col, p (e.g. oi_inputs.Graph)."""
+        return cls(g.n, g.row_ptr, g.col, g.p, stream)
+
+    def close(self):
+        if getattr(self, "h", None) is not None:
+            oi_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_probs(self, p):
+        dev = _is_device_tensor(p)
+        oi_graph_set_probs(self.h, p.contiguous() if dev else np.ascontiguousarray(p, np.float32),
+                           1 if dev else 0)
+
+    def stage1(self, seeds):
+        return oi_stage1_table(self.h, seeds)
+
+    def sample_fixed(self, seeds, count, first=0, stream=0, query_id=0, run_seed=RUN_SEED, want_e=False,
+                     device="cuda"):
+        """Y (and optionally E) of `count` samples as torch tensors on the GPU."""
+        import torch
+        y = torch.empty(count, dtype=torch.int32, device=device)
+        e = torch.empty(count, dtype=torch.int64, device=device) if want_e else None
+        r = oi_sample_fixed(self.h, query_id, seeds, stream, first, count, run_seed, y, e)
+        return y, e, r
+
+    def estimate(self, seeds, eps, delta, mode=OI_MODE_SOIEA, query_id=0, run_seed=RUN_SEED):
+        return oi_estimate(self.h, query_id, seeds, eps, delta, mode, run_seed)
+
+    def estimate_batch(self, seed_sets, eps, delta, mode=OI_MODE_SOIEA, query_ids=None, run_seed=RUN_SEED):
+        off = np.zeros(len(seed_sets) + 1, np.int64)
+        off[1:] = np.cumsum([len(s) for s in seed_sets])
+        seeds = np.concatenate([np.asarray(s, np.int32) for s in seed_sets]) if seed_sets else np.zeros(0, np.int32)
+        q = np.arange(len(seed_sets), dtype=np.uint32) if query_ids is None else np.asarray(query_ids, np.uint32)
+        return oi_estimate_batch(self.h, off, seeds, q, eps, delta, mode, run_seed)
+
+    def backward(self, seeds, count, grad_out, y_in=None, first=0, param=OI_PARAM_P, grad_scale=1.0,
+                 query_id=0, run_seed=RUN_SEED):
+        oi_backward(self.h, query_id, seeds, first, count, run_seed, y_in, param, grad_scale, grad_out)
+        return grad_out
+
+    def timing(self, enable=None):
+        if enable is not None:
+            oi_timing_enable(self.h, enable)
+        return oi_timing_get(self.h)
+
+    def tune(self, variant=-1, chunk=-1, round_max=-1):
+        oi_set_tuning(self.h, variant, chunk, round_max)

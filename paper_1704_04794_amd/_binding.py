@@ -1,0 +1,229 @@
+"""ctypes binding of include/oi.h.
+
+Argument marshalling only: every function forwards to the C entry point of
+the same name in liboi_hip.so; all computation happens in the library's HIP
+kernels.  Arrays may be numpy arrays (host memory) or torch tensors; device
+buffers must be CUDA (HIP) tensors of the graph's GPU.  If the library has
+not been built this module raises at import time: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liboi_hip.so")
+
+OI_OK, OI_EINVAL, OI_ERANGE, OI_ENOMEM, OI_EHIP, OI_ESTATE = 0, -1, -2, -3, -4, -5
+OI_MODE_SOIEA, OI_MODE_SIEA = 0, 1
+OI_PARAM_P, OI_PARAM_THETA = 0, 1
+
+
+class oi_result(C.Structure):
+    _fields_ = [
+        ("oi", C.c_double), ("is_", C.c_double), ("beta0", C.c_double), ("mu", C.c_double),
+        ("mu1", C.c_double),
+        ("T1", C.c_uint64), ("h1", C.c_uint64), ("nsigma", C.c_uint64), ("D_lo", C.c_uint64),
+        ("D_hi", C.c_uint64), ("T", C.c_uint64), ("hT", C.c_uint64),
+        ("samples_x", C.c_uint64), ("samples_xp", C.c_uint64), ("sum_y", C.c_uint64),
+        ("edges_examined", C.c_uint64), ("k", C.c_int64), ("l", C.c_int64),
+        ("gsra_only", C.c_int32), ("early", C.c_int32), ("status", C.c_int32), ("rounds", C.c_int32),
+    ]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_}
+        d["D"] = (int(self.D_hi) << 64) | int(self.D_lo)
+        return d
+
+
+class oi_timing(C.Structure):
+    _fields_ = [
+        ("small_ms", C.c_double), ("large_ms", C.c_double), ("other_ms", C.c_double),
+        ("small_launches", C.c_uint64), ("large_launches", C.c_uint64), ("samples", C.c_uint64),
+        ("deferred", C.c_uint64), ("sum_y", C.c_uint64), ("edges", C.c_uint64),
+        ("large_sum_y", C.c_uint64), ("large_edges", C.c_uint64),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class OiError(RuntimeError):
+    def __init__(self, fn, status, msg):
+        super().__init__(f"{fn} failed ({status}): {msg}")
+        self.status = status
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1704_04794_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    i64, u64, u32, i32, dbl, vp, ci = C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double, C.c_void_p, C.c_int
+    P = C.POINTER
+    sig = {
+        "oi_graph_create": [i64, i64, vp, vp, vp, ci, vp, P(vp)],
+        "oi_graph_set_probs": [vp, vp, ci],
+        "oi_set_stream": [vp, vp],
+        "oi_stage1_table": [vp, vp, i64, i64, P(i64), P(dbl), vp, vp, vp, vp],
+        "oi_sample_fixed": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
+        "oi_estimate": [vp, u32, vp, i64, dbl, dbl, ci, u32, P(oi_result)],
+        "oi_estimate_batch": [vp, i32, vp, vp, vp, dbl, dbl, ci, u32, vp],
+        "oi_backward": [vp, u32, vp, i64, u64, u64, u32, vp, ci, dbl, vp],
+        "oi_timing_enable": [vp, ci],
+        "oi_timing_get": [vp, P(oi_timing)],
+        "oi_set_tuning": [vp, ci, ci, i64],
+        "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
+    }
+    for name, args in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = ci
+    L.oi_graph_destroy.argtypes = [vp]
+    L.oi_graph_destroy.restype = None
+    L.oi_num_variants.argtypes = []
+    L.oi_num_variants.restype = ci
+    L.oi_last_error.argtypes = []
+    L.oi_last_error.restype = C.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+def lib():
+    return _lib
+
+
+def oi_last_error() -> str:
+    return _lib.oi_last_error().decode(errors="replace")
+
+
+def _check(fn, st):
+    if st != OI_OK:
+        raise OiError(fn, st, oi_last_error())
+
+
+def _ptr(x):
+    """Raw address of a numpy array or torch tensor (None -> NULL)."""
+    if x is None:
+        return None
+    if isinstance(x, np.ndarray):
+        return x.ctypes.data
+    return int(x.data_ptr())
+
+
+def _host(a, dtype):
+    return np.ascontiguousarray(np.asarray(a), dtype=dtype)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return torch.cuda.current_stream().cuda_stream
+        except Exception:  # pragma: no cover
+            pass
+        return None
+    return getattr(stream, "cuda_stream", stream)
+
+
+# ---------------------------------------------------------------------------
+# entry points (same names as the C ABI)
+# ---------------------------------------------------------------------------
+
+def oi_graph_create(n, m, row_ptr, col, p, device_ptrs=0, hip_stream=None):
+    h = C.c_void_p()
+    _check("oi_graph_create", _lib.oi_graph_create(int(n), int(m), _ptr(row_ptr), _ptr(col), _ptr(p),
+                                                    int(device_ptrs), _stream_handle(hip_stream), C.byref(h)))
+    return h
+
+
+def oi_graph_set_probs(g, p, device_ptr=0):
+    _check("oi_graph_set_probs", _lib.oi_graph_set_probs(g, _ptr(p), int(device_ptr)))
+
+
+def oi_set_stream(g, hip_stream):
+    _check("oi_set_stream", _lib.oi_set_stream(g, _stream_handle(hip_stream)))
+
+
+def oi_graph_destroy(g):
+    _lib.oi_graph_destroy(g)
+
+
+def oi_stage1_table(g, seeds, cap=1 << 24):
+    s = _host(seeds, np.int32)
+    l = C.c_int64()
+    b0 = C.c_double()
+    _check("oi_stage1_table", _lib.oi_stage1_table(g, _ptr(s), s.size, 0, C.byref(l), C.byref(b0),
+                                                    None, None, None, None))
+    L = l.value
+    v = np.zeros(L, np.int32)
+    P = np.zeros(L, np.float64)
+    cdf = np.zeros(L + 1, np.float64)
+    thr = np.zeros(L, np.uint64)
+    if L <= cap:
+        _check("oi_stage1_table", _lib.oi_stage1_table(g, _ptr(s), s.size, L, C.byref(l), C.byref(b0),
+                                                        _ptr(v), _ptr(P), _ptr(cdf), _ptr(thr)))
+    return dict(l=L, beta0=b0.value, v=v, P=P, cdf=cdf, thr=thr)
+
+
+def oi_sample_fixed(g, query_id, seeds, stream, first, count, run_seed, y_out=None, e_out=None):
+    s = _host(seeds, np.int32)
+    r = oi_result()
+    _check("oi_sample_fixed", _lib.oi_sample_fixed(g, int(query_id), _ptr(s), s.size, int(stream), int(first),
+                                                    int(count), int(run_seed), _ptr(y_out), _ptr(e_out),
+                                                    C.byref(r)))
+    return r.as_dict()
+
+
+def oi_estimate(g, query_id, seeds, eps, delta, mode, run_seed):
+    s = _host(seeds, np.int32)
+    r = oi_result()
+    _check("oi_estimate", _lib.oi_estimate(g, int(query_id), _ptr(s), s.size, float(eps), float(delta),
+                                            int(mode), int(run_seed), C.byref(r)))
+    return r.as_dict()
+
+
+def oi_estimate_batch(g, seed_off, seeds, query_ids, eps, delta, mode, run_seed):
+    off = _host(seed_off, np.int64)
+    s = _host(seeds, np.int32)
+    q = _host(query_ids, np.uint32)
+    nq = off.size - 1
+    out = (oi_result * nq)()
+    _check("oi_estimate_batch", _lib.oi_estimate_batch(g, nq, _ptr(off), _ptr(s), _ptr(q), float(eps),
+                                                        float(delta), int(mode), int(run_seed), out))
+    return [out[i].as_dict() for i in range(nq)]
+
+
+def oi_backward(g, query_id, seeds, first, count, run_seed, y_in, param, grad_scale, grad_out):
+    s = _host(seeds, np.int32)
+    _check("oi_backward", _lib.oi_backward(g, int(query_id), _ptr(s), s.size, int(first), int(count),
+                                            int(run_seed), _ptr(y_in), int(param), float(grad_scale),
+                                            _ptr(grad_out)))
+
+
+def oi_timing_enable(g, enable=True):
+    _check("oi_timing_enable", _lib.oi_timing_enable(g, int(bool(enable))))
+
+
+def oi_timing_get(g):
+    t = oi_timing()
+    _check("oi_timing_get", _lib.oi_timing_get(g, C.byref(t)))
+    return t.as_dict()
+
+
+def oi_set_tuning(g, variant=-1, chunk=-1, round_max=-1):
+    _check("oi_set_tuning", _lib.oi_set_tuning(g, int(variant), int(chunk), int(round_max)))
+
+
+def oi_num_variants():
+    return int(_lib.oi_num_variants())
+
+
+def oi_variant_info(v):
+    a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+    _check("oi_variant_info", _lib.oi_variant_info(int(v), C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+    return dict(slots_per_wave=a.value, hash_cap=b.value, ring_cap=c.value, rounds_per_pass=d.value)

@@ -1,0 +1,965 @@
+// HIP kernels for IICP sampling (Alg. 1), its score-function backward, and the
+// integer reductions the stopping rules need (Algs. 2 and 3).
+//
+// Sampling is split over two kernels:
+//   * small_kernel: persistent; every wavefront runs K samples at once, each
+//     with a visited set in LDS (open addressing) and a shared LDS ring of
+//     pending expansion items.  Each pass the wave gathers up to 64 items,
+//     load-balances their edge groups over its 64 lanes (prefix sum +
+//     binary search), draws one Philox block per group of four edges, and
+//     inserts the live, unvisited, non-seed targets.  A sample whose visited
+//     set would exceed the LDS capacity is abandoned and handed over by its
+//     flat index.
+//   * large_kernel: one 256-thread block per handed-over sample; it restarts
+//     the sample from its counter key with a global visited bitmap and a
+//     global queue.
+// Both produce the same visited set as the sequential algorithm, because
+// every coin is a pure function of (query, stream, sample, edge id): the set
+// of activated nodes is the closure of the Stage-1 set under live edges,
+// whatever order the edges are examined in.
+#include "oi_device.hpp"
+
+namespace oi {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) and the coin conventions
+// ---------------------------------------------------------------------------
+struct Words {
+  uint32_t w[4];
+};
+
+__device__ __forceinline__ Words philox_draw(uint32_t k0, uint32_t k1, uint32_t kind, uint32_t stream,
+                                             uint64_t s, uint64_t idx) {
+  uint32_t c0 = (uint32_t)idx, c1 = (uint32_t)(idx >> 32), c2 = (uint32_t)s;
+  uint32_t c3 = (kind << 28) | (stream << 27) | ((uint32_t)(s >> 32) & 0x07FFFFFFu);
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)b;
+    c3 = (uint32_t)a;
+    c0 = n0;
+    c2 = n2;
+  }
+  Words o;
+  o.w[0] = c0;
+  o.w[1] = c1;
+  o.w[2] = c2;
+  o.w[3] = c3;
+  return o;
+}
+
+// Live iff word < floor(p * 2^32).  p * 2^32 is exact in fp32 for p in [0, 1)
+// and the conversion truncates, which is the floor; p = 1 is always live.
+__device__ __forceinline__ bool edge_live(uint32_t word, float p) {
+  return p >= 1.0f || word < (uint32_t)(p * 4294967296.0f);
+}
+
+// Stage 1, line 2 of Alg. 1: t = U * beta_0, i = min{j : CDF_j > t}; if no
+// entry qualifies, the last entry with Pr[A_j] > 0.
+__device__ int64_t select_entry(const QueryDev& Q, uint32_t seed, uint32_t stream, uint64_t s) {
+  const Words d = philox_draw(Q.qid, seed, KIND_SELECT, stream, s, 0);
+  const uint64_t a = d.w[0] >> 5, b = d.w[1] >> 6;
+  const double U = (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
+  const double t = U * Q.beta0;
+  int64_t lo = 0, hi = Q.l;
+  while (lo < hi) {
+    const int64_t mid = lo + ((hi - lo) >> 1);
+    if (Q.cdf[mid + 1] > t)
+      hi = mid;
+    else
+      lo = mid + 1;
+  }
+  if (lo < Q.l) return lo;
+  for (int64_t j = Q.l - 1; j >= 0; --j)
+    if (Q.cdf[j + 1] > Q.cdf[j]) return j;
+  return -1;
+}
+
+__device__ __forceinline__ bool in_seed_set(const QueryDev& Q, int32_t v) {
+  if (Q.k == 1) return v == Q.s0;
+  uint32_t h = mix32((uint32_t)v) & Q.smask;
+  while (true) {
+    const int32_t c = Q.shash[h];
+    if (c == v) return true;
+    if (c < 0) return false;
+    h = (h + 1) & Q.smask;
+  }
+}
+
+__device__ __forceinline__ uint32_t find_segment(const SampleLaunch& A, uint64_t f) {
+  int32_t lo = 0, hi = A.nseg - 1;  // last segment with flat0 <= f
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (A.segs[mid].flat0 <= f)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t lane_prefix(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+template <typename T>
+__device__ __forceinline__ T uniform(T v) {
+  return (T)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t y = __shfl_up(x, d, 64);
+    if (lane >= d) x += y;
+  }
+  return x;
+}
+
+// ---------------------------------------------------------------------------
+// small_kernel
+// ---------------------------------------------------------------------------
+// Ring items (64 bits): a = node id (node item) or next Stage-1 entry index
+// (Stage-1 item) in bits 0..31; group offset from the row's first group in
+// bits 32..58 (node items); kind in bits 59..60; slot in bits 61..63.
+constexpr uint32_t ITEM_NODE = 0;
+constexpr uint32_t ITEM_STAGE1 = 1;
+
+__device__ __forceinline__ uint64_t mk_item(uint32_t slot, uint32_t kind, uint32_t off, uint32_t a) {
+  return ((uint64_t)slot << 61) | ((uint64_t)kind << 59) | ((uint64_t)off << 32) | (uint64_t)a;
+}
+__device__ __forceinline__ uint32_t item_slot(uint64_t it) { return (uint32_t)(it >> 61); }
+__device__ __forceinline__ uint32_t item_kind(uint64_t it) { return (uint32_t)(it >> 59) & 3u; }
+__device__ __forceinline__ uint32_t item_off(uint64_t it) { return (uint32_t)(it >> 32) & 0x07FFFFFFu; }
+__device__ __forceinline__ uint32_t item_a(uint64_t it) { return (uint32_t)it; }
+
+template <int K, int HCAP, int RCAP>
+struct SmallLds {
+  int32_t hash[K][HCAP];
+  uint64_t ring[RCAP];
+  uint64_t it_item[64];
+  int64_t it_eb[64];
+  int64_t it_ee[64];
+  uint32_t it_g0[64];
+  uint32_t it_scan[64];
+  uint64_t s_f[K];
+  uint64_t s_s[K];
+  unsigned long long s_E[K];
+  uint32_t s_q[K];
+  uint32_t s_seg[K];
+  uint32_t s_stream[K];
+  uint32_t s_cnt[K];
+  uint32_t s_pend[K];
+  uint32_t s_new[K];
+  uint32_t s_active[K];
+  uint32_t s_y[K];
+  int32_t s_vi[K];
+  uint32_t s_i[K];
+  uint32_t head, tail;
+};
+
+template <int HCAP>
+__device__ __forceinline__ uint32_t hslot(int32_t v) {
+  constexpr int LOG = __builtin_ctz(HCAP);
+  return ((uint32_t)v * 0x9E3779B1u) >> (32 - LOG);
+}
+
+template <int HCAP>
+__device__ __forceinline__ bool hash_contains(const int32_t* h, int32_t v) {
+  uint32_t p = hslot<HCAP>(v);
+  while (true) {
+    const int32_t c = h[p];
+    if (c == v) return true;
+    if (c < 0) return false;
+    p = (p + 1) & (HCAP - 1);
+  }
+}
+
+template <int HCAP>
+__device__ __forceinline__ bool hash_insert(int32_t* h, int32_t v) {
+  uint32_t p = hslot<HCAP>(v);
+  while (true) {
+    int32_t c = h[p];
+    if (c == v) return false;
+    if (c < 0) {
+      c = atomicCAS(&h[p], -1, v);
+      if (c < 0) return true;
+      if (c == v) return false;
+    }
+    p = (p + 1) & (HCAP - 1);
+  }
+}
+
+template <int K, int HCAP, int RCAP, int R, bool BWD>
+__global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
+  constexpr int WPB = 4;
+  constexpr uint32_t CMAX = RCAP / K - 1;  // visited nodes one slot may hold
+  static_assert(2 * CMAX <= HCAP, "LDS hash load factor must stay <= 1/2");
+  static_assert(K <= 8, "slot field is 3 bits");
+  constexpr uint32_t B = 64u * R;          // edge groups per pass
+  __shared__ SmallLds<K, HCAP, RCAP> lds_all[WPB];
+  SmallLds<K, HCAP, RCAP>& W = lds_all[threadIdx.x >> 6];
+  const int lane = threadIdx.x & 63;
+
+  if (lane < K) {
+    W.s_active[lane] = 0;
+    W.s_new[lane] = 0;
+  }
+  if (lane == 0) {
+    W.head = 0;
+    W.tail = 0;
+  }
+  wave_sync();
+
+  uint64_t cur = 0, cend = 0;
+  bool exhausted = false;
+  uint32_t acc_seg = 0xFFFFFFFFu;
+  unsigned long long acc_y = 0, acc_e = 0;
+
+  while (true) {
+    // ---- refill free slots from the work counter ----------------------
+    uint32_t newmask = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (uniform(W.s_active[k]) == 0u) {
+        if (cur >= cend && !exhausted) {
+          unsigned long long c = 0;
+          if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.chunk);
+          c = uniform64(__shfl(c, 0, 64));
+          if (c >= A.total) {
+            exhausted = true;
+          } else {
+            cur = c;
+            cend = c + A.chunk < A.total ? c + A.chunk : A.total;
+          }
+        }
+        if (cur < cend) {
+          if (lane == 0) W.s_f[k] = cur;
+          ++cur;
+          newmask |= 1u << k;
+        }
+      }
+    }
+    wave_sync();
+    if (newmask) {
+      // lanes 0..K-1 start their slot's sample: Stage 1, lines 2-3 of Alg. 1
+      if (lane < K && ((newmask >> lane) & 1u)) {
+        const uint64_t f = W.s_f[lane];
+        const uint32_t sg = find_segment(A, f);
+        const Segment S = A.segs[sg];
+        const QueryDev& Q = A.qs[S.q];
+        const uint64_t s = S.first + (f - S.flat0);
+        uint32_t y = 0;
+        bool start = true;
+        if (BWD) {
+          y = A.y_in[S.out_off + (f - S.flat0)];
+          if (y > CMAX) {  // known too large for LDS: straight to the large kernel
+            const unsigned int pos = atomicAdd(A.ndeferred, 1u);
+            A.deferred[pos] = f;
+            start = false;
+          }
+        }
+        if (start) {
+          int64_t i = select_entry(Q, A.seed, S.stream, s);
+          if (i < 0) {
+            atomicOr(A.err, 1u);
+            i = 0;
+          }
+          const int32_t vi = Q.tab[i >> 2].v[i & 3];
+          W.s_s[lane] = s;
+          W.s_q[lane] = S.q;
+          W.s_seg[lane] = sg;
+          W.s_stream[lane] = S.stream;
+          W.s_E[lane] = (unsigned long long)(Q.l - 1 - i);
+          W.s_cnt[lane] = 1;
+          W.s_pend[lane] = (i + 1 < Q.l) ? 2u : 1u;
+          W.s_new[lane] = 0;
+          W.s_y[lane] = y;
+          W.s_vi[lane] = vi;
+          W.s_i[lane] = (uint32_t)i;
+          W.s_active[lane] = 1;
+          if (BWD) atomicAdd(&A.acc_tab[i], (unsigned long long)y);
+        } else {
+          W.s_active[lane] = 0;
+        }
+      }
+      wave_sync();
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if ((newmask >> k) & 1u) {
+          for (int h = lane; h < HCAP; h += 64) W.hash[k][h] = -1;
+        }
+      }
+      wave_sync();
+      if (lane < K && ((newmask >> lane) & 1u) && W.s_active[lane]) {
+        const int32_t vi = W.s_vi[lane];
+        W.hash[lane][hslot<HCAP>(vi)] = vi;
+        const uint32_t i = W.s_i[lane];
+        const QueryDev& Q = A.qs[W.s_q[lane]];
+        const bool more = (int64_t)i + 1 < Q.l;
+        const uint32_t pos = atomicAdd(&W.tail, more ? 2u : 1u);
+        W.ring[pos & (RCAP - 1)] = mk_item(lane, ITEM_NODE, 0, (uint32_t)vi);
+        if (more) W.ring[(pos + 1) & (RCAP - 1)] = mk_item(lane, ITEM_STAGE1, 0, i + 1);
+      }
+      wave_sync();
+    }
+    uint32_t anyactive = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) anyactive |= uniform(W.s_active[k]);
+    if (!anyactive) {
+      if (exhausted) break;
+      continue;
+    }
+
+    // ---- gather up to 64 items and cut them to B edge groups -------------
+    const uint32_t head = uniform(W.head), tail = uniform(W.tail);
+    const uint32_t avail = tail - head;
+    const uint32_t nit = avail < 64u ? avail : 64u;
+    if (nit == 0) {  // active slots always have queued items; never spin if not
+      if (lane == 0) atomicOr(A.err, 4u);
+      if (lane < K) W.s_active[lane] = 0;
+      wave_sync();
+      continue;
+    }
+    uint64_t item = 0;
+    uint32_t ntask = 0, kind = 0, slot = 0, off = 0, a = 0, g0 = 0;
+    int64_t eb = 0, ee = 0;
+    if ((uint32_t)lane < nit) {
+      item = W.ring[(head + lane) & (RCAP - 1)];
+      kind = item_kind(item);
+      slot = item_slot(item);
+      off = item_off(item);
+      a = item_a(item);
+      if (kind == ITEM_NODE) {
+        eb = A.row_ptr[a];
+        ee = A.row_ptr[a + 1];
+        if (ee > eb) {
+          g0 = (uint32_t)(eb >> 2) + off;
+          ntask = (uint32_t)((ee + 3) >> 2) - g0;
+        }
+      } else {
+        const QueryDev& Q = A.qs[W.s_q[slot]];
+        eb = a;
+        ee = Q.l;
+        g0 = a >> 2;
+        ntask = (uint32_t)((Q.l + 3) >> 2) - g0;
+      }
+    }
+    const uint32_t sc = wave_incl_scan(ntask, lane);
+    const uint32_t total = uniform(__shfl(sc, nit ? (int)nit - 1 : 0, 64));
+    uint32_t take = ntask;
+    bool consumed = (uint32_t)lane < nit;
+    uint32_t cut = nit;
+    if (total > B) {
+      const unsigned long long m = __ballot((uint32_t)lane < nit && sc > B);
+      cut = (uint32_t)__ffsll((long long)m) - 1u;
+      if ((uint32_t)lane == cut) {
+        take = B - (sc - ntask);
+        consumed = false;
+      } else if ((uint32_t)lane > cut) {
+        take = 0;
+        consumed = false;
+      }
+    }
+    if ((uint32_t)lane < nit) {
+      if (kind == ITEM_NODE && off == 0 && (consumed || take > 0))
+        atomicAdd(&W.s_E[slot], (unsigned long long)(ee - eb));
+      if (consumed) atomicSub(&W.s_pend[slot], 1u);
+      if ((uint32_t)lane == cut) {
+        // the remainder starts at the first group not taken; a Stage-1 item
+        // keeps its exact first entry while none of its groups was taken
+        const uint64_t rem = kind == ITEM_NODE ? mk_item(slot, ITEM_NODE, off + take, a)
+                                               : mk_item(slot, ITEM_STAGE1, 0, take ? (g0 + take) * 4u : a);
+        W.ring[(head + cut) & (RCAP - 1)] = rem;
+      }
+    }
+    W.it_item[lane] = item;
+    W.it_eb[lane] = eb;
+    W.it_ee[lane] = ee;
+    W.it_g0[lane] = g0;
+    W.it_scan[lane] = sc < B ? sc : B;
+    if (lane == 0) W.head = head + cut;
+    wave_sync();
+    const uint32_t ntot = total < B ? total : B;
+
+    // ---- phase A: coins for every task, count new live targets -----------
+    uint32_t mask[R];
+    int32_t tv[R][4];
+    uint32_t tslot[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      mask[r] = 0;
+      tslot[r] = 0;
+      const uint32_t t = (uint32_t)(r * 64 + lane);
+      if (t < ntot) {
+        int lo = 0, hi = (int)nit - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (W.it_scan[mid] > t)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        const uint64_t it = W.it_item[lo];
+        const uint32_t sl = item_slot(it);
+        const uint32_t kd = item_kind(it);
+        const uint32_t base = lo ? W.it_scan[lo - 1] : 0u;
+        const uint32_t g = W.it_g0[lo] + (t - base);
+        const int64_t lo_e = W.it_eb[lo], hi_e = W.it_ee[lo];
+        const QueryDev& Q = A.qs[W.s_q[sl]];
+        const uint64_t s = W.s_s[sl];
+        const uint32_t stream = W.s_stream[sl];
+        const int32_t* hs = W.hash[sl];
+        tslot[r] = sl;
+        uint32_t mk = 0;
+        if (kd == ITEM_NODE) {
+          const Words d = philox_draw(Q.qid, A.seed, KIND_EDGE, stream, s, g);
+          const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
+          const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
+          const int32_t va[4] = {vv.x, vv.y, vv.z, vv.w};
+          const float pa[4] = {pp.x, pp.y, pp.z, pp.w};
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int64_t e = 4 * (int64_t)g + b;
+            tv[r][b] = va[b];
+            if (e >= lo_e && e < hi_e) {
+              const bool live = edge_live(d.w[b], pa[b]);
+              if (BWD) {
+                if (!in_seed_set(Q, va[b])) {
+                  const unsigned long long y = W.s_y[sl];
+                  atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
+                  if (live && !hash_contains<HCAP>(hs, va[b])) mk |= 1u << b;
+                }
+              } else if (live && !in_seed_set(Q, va[b]) && !hash_contains<HCAP>(hs, va[b])) {
+                mk |= 1u << b;
+              }
+            }
+          }
+        } else {
+          const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, stream, s, g);
+          const TabGroup T = Q.tab[g];
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int64_t j = 4 * (int64_t)g + b;
+            tv[r][b] = T.v[b];
+            if (j >= lo_e && j < hi_e && (uint64_t)d.w[b] < T.thr[b]) {
+              if (BWD) atomicAdd(&A.acc_tab[j], (unsigned long long)W.s_y[sl]);
+              if (!hash_contains<HCAP>(hs, T.v[b])) mk |= 1u << b;
+            }
+          }
+        }
+        mask[r] = mk;
+        if (mk) atomicAdd(&W.s_new[sl], (uint32_t)__popc(mk));
+      }
+    }
+    wave_sync();
+
+    // ---- hand over samples that would outgrow the LDS set ----------------
+    // (In the backward every started sample has Y <= CMAX, so this can only
+    // trigger if y_in disagrees with the recomputation: flag it and drop the
+    // sample rather than overfill the set.)
+    uint32_t defmask = 0;
+    {
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        if (uniform(W.s_active[k]) && uniform(W.s_cnt[k]) + uniform(W.s_new[k]) > CMAX) defmask |= 1u << k;
+      }
+      if (defmask) {
+        if (lane == 0) {
+          for (int k = 0; k < K; ++k) {
+            if ((defmask >> k) & 1u) {
+              if (BWD) {
+                atomicOr(A.err, 8u);
+              } else {
+                const unsigned int pos = atomicAdd(A.ndeferred, 1u);
+                A.deferred[pos] = W.s_f[k];
+              }
+              W.s_active[k] = 0;
+            }
+          }
+        }
+        // drop the handed-over slots' items from the ring (stable compaction)
+        const uint32_t h0 = uniform(W.head), n0 = uniform(W.tail) - h0;
+        uint32_t w = h0;
+        for (uint32_t i0 = 0; i0 < n0; i0 += 64) {
+          const uint32_t i = i0 + lane;
+          const bool valid = i < n0;
+          const uint64_t it = valid ? W.ring[(h0 + i) & (RCAP - 1)] : 0ull;
+          const bool keep = valid && !((defmask >> item_slot(it)) & 1u);
+          const unsigned long long bal = __ballot(keep);
+          wave_sync();
+          if (keep) W.ring[(w + lane_prefix(bal)) & (RCAP - 1)] = it;
+          w += (uint32_t)__popcll(bal);
+          wave_sync();
+        }
+        if (lane == 0) W.tail = w;
+      }
+    }
+    if (lane < K) W.s_new[lane] = 0;
+    wave_sync();
+
+    // ---- phase B: insert new targets and queue them ----------------------
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (mask[r] && !((defmask >> tslot[r]) & 1u)) {
+        const uint32_t sl = tslot[r];
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          if ((mask[r] >> b) & 1u) {
+            const int32_t v = tv[r][b];
+            if (hash_insert<HCAP>(W.hash[sl], v)) {
+              atomicAdd(&W.s_cnt[sl], 1u);
+              atomicAdd(&W.s_pend[sl], 1u);
+              const uint32_t pos = atomicAdd(&W.tail, 1u);
+              W.ring[pos & (RCAP - 1)] = mk_item(sl, ITEM_NODE, 0, (uint32_t)v);
+            }
+          }
+        }
+      }
+    }
+    wave_sync();
+
+    // ---- finished samples --------------------------------------------------
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      if (uniform(W.s_active[k]) && uniform(W.s_pend[k]) == 0u) {
+        const uint32_t cnt = uniform(W.s_cnt[k]);
+        const uint64_t E = uniform64(W.s_E[k]);
+        const uint32_t sg = uniform(W.s_seg[k]);
+        if (lane == 0) {
+          const Segment& S = A.segs[sg];
+          const uint64_t idx = S.out_off + (W.s_f[k] - S.flat0);
+          if (BWD) {
+            if (cnt != W.s_y[k]) atomicOr(A.err, 2u);
+          } else {
+            A.y_out[idx] = cnt;
+            if (A.e_out) A.e_out[idx] = E;
+          }
+          W.s_active[k] = 0;
+        }
+        if (sg != acc_seg) {
+          if (lane == 0 && acc_seg != 0xFFFFFFFFu) {
+            atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
+            atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
+          }
+          acc_seg = sg;
+          acc_y = 0;
+          acc_e = 0;
+        }
+        acc_y += cnt;
+        acc_e += E;
+      }
+    }
+    wave_sync();
+  }
+  if (lane == 0 && acc_seg != 0xFFFFFFFFu) {
+    atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
+    atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// large_kernel: one block per handed-over sample, global bitmap + queue
+// ---------------------------------------------------------------------------
+constexpr int LB = 256;
+
+__device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, int tid, uint32_t* total) {
+  const int lane = tid & 63, wid = tid >> 6;
+  x = wave_incl_scan(x, lane);
+  if (lane == 63) wtot[wid] = x;
+  __syncthreads();
+  uint32_t add = 0, tot = 0;
+#pragma unroll
+  for (int w = 0; w < LB / 64; ++w) {
+    const uint32_t v = wtot[w];
+    if (w < wid) add += v;
+    tot += v;
+  }
+  *total = tot;
+  __syncthreads();
+  return x + add;
+}
+
+template <bool BWD>
+__global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
+  __shared__ uint32_t s_tail;
+  __shared__ unsigned long long s_E;
+  __shared__ uint32_t wtot[LB / 64];
+  __shared__ uint32_t it_scan[LB];
+  __shared__ int64_t it_eb[LB];
+  __shared__ int64_t it_ee[LB];
+  __shared__ uint32_t it_g0[LB];
+  __shared__ int64_t s_i;
+  const int tid = threadIdx.x;
+  uint32_t* bits = A.bits + (int64_t)blockIdx.x * A.bits_words;
+  int32_t* queue = A.queue + (int64_t)blockIdx.x * A.n;
+  const uint32_t nd = *A.ndeferred;
+  for (uint32_t di = blockIdx.x; di < nd; di += gridDim.x) {
+    const uint64_t f = A.deferred[di];
+    const uint32_t sg = find_segment(A, f);
+    const Segment S = A.segs[sg];
+    const QueryDev& Q = A.qs[S.q];
+    const uint64_t s = S.first + (f - S.flat0);
+    const uint64_t oidx = S.out_off + (f - S.flat0);
+    const unsigned long long y = BWD ? A.y_in[oidx] : 0ull;
+    if (tid == 0) {
+      int64_t i = select_entry(Q, A.seed, S.stream, s);
+      if (i < 0) {
+        atomicOr(A.err, 1u);
+        i = 0;
+      }
+      const int32_t vi = Q.tab[i >> 2].v[i & 3];
+      queue[0] = vi;
+      atomicOr(&bits[vi >> 5], 1u << (vi & 31));
+      s_tail = 1;
+      s_E = (unsigned long long)(Q.l - 1 - i);
+      s_i = i;
+      if (BWD) atomicAdd(&A.acc_tab[i], y);
+    }
+    __syncthreads();
+    const int64_t i = s_i;
+    // Stage 1, lines 4-6
+    const int64_t gend = (Q.l + 3) >> 2;
+    for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += LB) {
+      const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
+      const TabGroup T = Q.tab[g];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t j = 4 * g + b;
+        if (j > i && j < Q.l && (uint64_t)d.w[b] < T.thr[b]) {
+          if (BWD) atomicAdd(&A.acc_tab[j], y);
+          const int32_t v = T.v[b];
+          const uint32_t bit = 1u << (v & 31);
+          if (!(atomicOr(&bits[v >> 5], bit) & bit)) queue[atomicAdd(&s_tail, 1u)] = v;
+        }
+      }
+    }
+    __syncthreads();
+    // Stage 2, lines 7-12: expand the queue in batches of LB nodes
+    uint32_t head = 0;
+    while (true) {
+      const uint32_t tail = s_tail;
+      __syncthreads();
+      if (head >= tail) break;
+      const uint32_t nb = tail - head < (uint32_t)LB ? tail - head : (uint32_t)LB;
+      uint32_t ntask = 0, g0 = 0;
+      int64_t eb = 0, ee = 0;
+      if ((uint32_t)tid < nb) {
+        const int32_t u = queue[head + tid];
+        eb = A.row_ptr[u];
+        ee = A.row_ptr[u + 1];
+        if (ee > eb) {
+          g0 = (uint32_t)(eb >> 2);
+          ntask = (uint32_t)((ee + 3) >> 2) - g0;
+          atomicAdd(&s_E, (unsigned long long)(ee - eb));
+        }
+      }
+      uint32_t total;
+      const uint32_t sc = block_incl_scan(ntask, wtot, tid, &total);
+      it_scan[tid] = sc;
+      it_eb[tid] = eb;
+      it_ee[tid] = ee;
+      it_g0[tid] = g0;
+      __syncthreads();
+      for (uint32_t t = tid; t < total; t += LB) {
+        int lo = 0, hi = (int)nb - 1;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (it_scan[mid] > t)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        const uint32_t base = lo ? it_scan[lo - 1] : 0u;
+        const uint32_t g = it_g0[lo] + (t - base);
+        const int64_t lo_e = it_eb[lo], hi_e = it_ee[lo];
+        const Words d = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, g);
+        const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
+        const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
+        const int32_t va[4] = {vv.x, vv.y, vv.z, vv.w};
+        const float pa[4] = {pp.x, pp.y, pp.z, pp.w};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t e = 4 * (int64_t)g + b;
+          if (e >= lo_e && e < hi_e) {
+            const bool live = edge_live(d.w[b], pa[b]);
+            if (BWD) {
+              if (!in_seed_set(Q, va[b])) {
+                atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
+                if (live) {
+                  const int32_t v = va[b];
+                  const uint32_t bit = 1u << (v & 31);
+                  if (!(atomicOr(&bits[v >> 5], bit) & bit)) queue[atomicAdd(&s_tail, 1u)] = v;
+                }
+              }
+            } else if (live && !in_seed_set(Q, va[b])) {
+              const int32_t v = va[b];
+              const uint32_t bit = 1u << (v & 31);
+              if (!(atomicOr(&bits[v >> 5], bit) & bit)) queue[atomicAdd(&s_tail, 1u)] = v;
+            }
+          }
+        }
+      }
+      head += nb;
+      __syncthreads();
+    }
+    const uint32_t Y = s_tail;
+    if (tid == 0) {
+      if (BWD) {
+        if (Y != y) atomicOr(A.err, 2u);
+      } else {
+        A.y_out[oidx] = Y;
+        if (A.e_out) A.e_out[oidx] = s_E;
+      }
+      atomicAdd(&A.seg_sums[2 * sg], (unsigned long long)Y);
+      atomicAdd(&A.seg_sums[2 * sg + 1], s_E);
+      atomicAdd(&A.large_sums[0], (unsigned long long)Y);
+      atomicAdd(&A.large_sums[1], s_E);
+    }
+    for (uint32_t t = tid; t < Y; t += LB) bits[queue[t] >> 5] = 0u;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// reductions for the stopping rules
+// ---------------------------------------------------------------------------
+// Sum of each chunk of `ch` consecutive Y values.
+__global__ void __launch_bounds__(256) chunk_sums_kernel(const uint32_t* y, uint64_t count, uint32_t ch,
+                                                         unsigned long long* out) {
+  __shared__ unsigned long long part[4];
+  const uint64_t c = blockIdx.x;
+  const uint64_t b = c * ch;
+  const uint64_t e = b + ch < count ? b + ch : count;
+  unsigned long long s = 0;
+  for (uint64_t i = b + threadIdx.x; i < e; i += 256) s += y[i];
+#pragma unroll
+  for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) out[c] = part[0] + part[1] + part[2] + part[3];
+}
+
+// 128-bit sums of (y[2i] - y[2i+1])^2 per pair segment.  Each term is below
+// 2^62; partial sums are carried as (lo, hi) pairs.
+struct PairSeg {
+  uint64_t out_off;  // first Y of the segment in y
+  uint64_t npairs;
+  uint64_t flat0;    // prefix over segments, in pairs
+  uint32_t acc;      // accumulator index (2 words each)
+  uint32_t pad;
+};
+
+__device__ __forceinline__ void add128(unsigned long long& lo, unsigned long long& hi, unsigned long long xlo,
+                                       unsigned long long xhi) {
+  const unsigned long long n = lo + xlo;
+  hi += xhi + (n < lo ? 1ull : 0ull);
+  lo = n;
+}
+
+__global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const PairSeg* ps, int32_t nps,
+                                                      uint64_t total, unsigned long long* acc) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int32_t cur = -1;
+  unsigned long long lo = 0, hi = 0;
+  for (; i < total; i += stride) {
+    int32_t a = 0, b = nps - 1;
+    while (a < b) {
+      const int32_t mid = (a + b + 1) >> 1;
+      if (ps[mid].flat0 <= i)
+        a = mid;
+      else
+        b = mid - 1;
+    }
+    if (a != cur) {
+      if (cur >= 0 && (lo | hi)) {
+        const unsigned long long old = atomicAdd(&acc[2 * ps[cur].acc], lo);
+        atomicAdd(&acc[2 * ps[cur].acc + 1], hi + (old + lo < old ? 1ull : 0ull));
+      }
+      cur = a;
+      lo = hi = 0;
+    }
+    const uint64_t p = ps[a].out_off + 2 * (i - ps[a].flat0);
+    const uint32_t y0 = y[p], y1 = y[p + 1];
+    const unsigned long long d = y0 > y1 ? (unsigned long long)(y0 - y1) : (unsigned long long)(y1 - y0);
+    add128(lo, hi, d * d, 0);
+  }
+  if (cur >= 0 && (lo | hi)) {
+    const unsigned long long old = atomicAdd(&acc[2 * ps[cur].acc], lo);
+    atomicAdd(&acc[2 * ps[cur].acc + 1], hi + (old + lo < old ? 1ull : 0ull));
+  }
+}
+
+// ---------------------------------------------------------------------------
+// backward finishing: integer Y-sums -> fp32 gradient
+// ---------------------------------------------------------------------------
+// Stage-2 edges: g_p = scale * (L/p - D/(1-p)), g_theta = scale * (L(1-p) - D p).
+__global__ void __launch_bounds__(256) bwd_edges_kernel(const EdgeGroup* eg, int64_t m,
+                                                        const unsigned long long* acc_live,
+                                                        const unsigned long long* acc_dead, double scale,
+                                                        int theta, float* grad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+    const double p = (double)eg[e >> 2].p[e & 3];
+    const unsigned long long L = acc_live[e], D = acc_dead[e];
+    double g = 0.0;
+    if (theta) {
+      g = scale * ((double)L * (1.0 - p) - (double)D * p);
+    } else {
+      double a = 0.0, b = 0.0;
+      if (L) a = (double)L / p;
+      if (D) b = (double)D / (1.0 - p);
+      g = scale * (a - b);
+    }
+    grad[e] = (float)g;
+  }
+}
+
+// S-edges into Stage-1 entry j: x_j = 1 contributes A_j * prod_{f != e}(1 - p_f) / P_j,
+// x_j = 0 contributes -B_j / (1 - p_e), B_j = sumY - A_j.
+__global__ void __launch_bounds__(256) bwd_stage1_kernel(const EdgeGroup* eg, const int64_t* se_off,
+                                                         const int64_t* se, const double* P, int64_t l,
+                                                         const unsigned long long* acc_tab,
+                                                         unsigned long long sumY, double scale, int theta,
+                                                         float* grad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < l; j += stride) {
+    const unsigned long long Aj = acc_tab[j], Bj = sumY - Aj;
+    const int64_t b0 = se_off[j], b1 = se_off[j + 1];
+    for (int64_t a = b0; a < b1; ++a) {
+      const int64_t e = se[a];
+      const double pe = (double)eg[e >> 2].p[e & 3];
+      double live = 0.0, dead = 0.0;
+      if (Aj) {
+        double prod = 1.0;
+        for (int64_t c = b0; c < b1; ++c)
+          if (c != a) {
+            const int64_t f = se[c];
+            prod = prod * (1.0 - (double)eg[f >> 2].p[f & 3]);
+          }
+        live = (double)Aj * prod / P[j];
+      }
+      double g;
+      if (theta) {
+        if (Bj) dead = (double)Bj * pe;
+        g = scale * (live * pe * (1.0 - pe) - dead);
+      } else {
+        if (Bj) dead = (double)Bj / (1.0 - pe);
+        g = scale * (live - dead);
+      }
+      grad[e] = (float)g;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host-callable launchers
+// ---------------------------------------------------------------------------
+struct SmallVariant {
+  const void* fwd;
+  const void* bwd;
+  int k, hcap, rcap, r;
+};
+
+#define OI_VARIANT(K, H, RC, R) \
+  {reinterpret_cast<const void*>(&small_kernel<K, H, RC, R, false>), \
+   reinterpret_cast<const void*>(&small_kernel<K, H, RC, R, true>), K, H, RC, R}
+
+static const SmallVariant kVariants[] = {
+    OI_VARIANT(4, 256, 512, 2),
+    OI_VARIANT(8, 128, 512, 2),
+    OI_VARIANT(2, 512, 512, 2),
+    OI_VARIANT(4, 256, 512, 1),
+    OI_VARIANT(4, 256, 512, 4),
+    OI_VARIANT(8, 256, 1024, 2),
+};
+
+int num_small_variants() { return (int)(sizeof(kVariants) / sizeof(kVariants[0])); }
+
+void small_variant_info(int v, int* k, int* hcap, int* rcap, int* r) {
+  const SmallVariant& s = kVariants[v];
+  *k = s.k;
+  *hcap = s.hcap;
+  *rcap = s.rcap;
+  *r = s.r;
+}
+
+hipError_t small_occupancy(int v, bool bwd, int* blocks_per_cu) {
+  const SmallVariant& s = kVariants[v];
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, bwd ? s.bwd : s.fwd, 256, 0);
+}
+
+hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
+  const SmallVariant& s = kVariants[v];
+  void* args[] = {const_cast<SampleLaunch*>(&A)};
+  return hipLaunchKernel(bwd ? s.bwd : s.fwd, dim3(blocks), dim3(256), args, 0, st);
+}
+
+hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
+  if (bwd)
+    hipLaunchKernelGGL(large_kernel<true>, dim3(blocks), dim3(LB), 0, st, A);
+  else
+    hipLaunchKernelGGL(large_kernel<false>, dim3(blocks), dim3(LB), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, unsigned long long* out,
+                             hipStream_t st) {
+  const uint64_t nc = (count + ch - 1) / ch;
+  if (nc == 0) return hipSuccess;
+  hipLaunchKernelGGL(chunk_sums_kernel, dim3((unsigned)nc), dim3(256), 0, st, y, count, ch, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
+                          hipStream_t st) {
+  if (total == 0) return hipSuccess;
+  uint64_t blocks = (total + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(pair_sq_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y,
+                     reinterpret_cast<const PairSeg*>(ps), nps, total, acc);
+  return hipGetLastError();
+}
+
+size_t pair_seg_size() { return sizeof(PairSeg); }
+
+hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L,
+                            const unsigned long long* D, double scale, int theta, float* grad, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  int64_t blocks = (m + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, eg, m, L, D, scale, theta, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const int64_t* se, const double* P,
+                             int64_t l, const unsigned long long* acc_tab, unsigned long long sumY, double scale,
+                             int theta, float* grad, hipStream_t st) {
+  if (l == 0) return hipSuccess;
+  int64_t blocks = (l + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(bwd_stage1_kernel, dim3((unsigned)blocks), dim3(256), 0, st, eg, se_off, se, P, l, acc_tab,
+                     sumY, scale, theta, grad);
+  return hipGetLastError();
+}
+
+}  // namespace oi

@@ -1,0 +1,995 @@
+// Host side of the C ABI in include/oi.h: graph upload, Stage-1 tables,
+// sampling launches, the GSRA/RSA controller (Algs. 2-5) and the backward.
+//
+// Build with -ffp-contract=off: every fp64 expression below is evaluated
+// exactly as written (left to right, no fused multiply-add), which is part
+// of the sampler's specification (selection thresholds, stopping rules).
+#include "oi.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "oi_device.hpp"
+
+namespace oi {
+int num_small_variants();
+void small_variant_info(int v, int* k, int* hcap, int* rcap, int* r);
+hipError_t small_occupancy(int v, bool bwd, int* blocks_per_cu);
+hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
+hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
+hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, unsigned long long* out, hipStream_t st);
+hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
+                          hipStream_t st);
+size_t pair_seg_size();
+hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L, const unsigned long long* D,
+                            double scale, int theta, float* grad, hipStream_t st);
+hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
+                             const unsigned long long* acc_tab, unsigned long long sumY, double scale, int theta,
+                             float* grad, hipStream_t st);
+}  // namespace oi
+
+namespace {
+
+thread_local std::string g_err;
+
+oi_status fail(oi_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define OI_TRY(expr)                    \
+  do {                                  \
+    oi_status st_ = (expr);             \
+    if (st_ != OI_OK) return st_;       \
+  } while (0)
+
+#define HIP_TRY(expr)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (expr);                                                                       \
+    if (e_ != hipSuccess)                                                                         \
+      return fail(e_ == hipErrorOutOfMemory ? OI_ENOMEM : OI_EHIP,                                \
+                  std::string(#expr) + " failed: " + hipGetErrorString(e_));                      \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b == 0) b = 16;
+    if (bytes >= b) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc(&p, b);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
+constexpr uint32_t kChunk = 4096;        // Y values per chunk sum (stopping-rule bookkeeping)
+constexpr uint64_t kMaxSample = 1ull << 59;
+
+}  // namespace
+
+struct oi_graph {
+  int64_t n = 0, m = 0, ngroups = 0;
+  hipStream_t stream = nullptr;
+  int device = 0;
+  int cus = 256;
+  std::vector<int64_t> row_ptr;
+  std::vector<int32_t> col;
+  std::vector<float> p;
+  DevBuf d_row_ptr, d_eg;
+  // per-launch workspaces
+  DevBuf d_y, d_def, d_ctl, d_segs, d_qs, d_sums, d_chunks, d_pairs, d_pacc, d_bits, d_queue;
+  int large_blocks = 0;
+  int variant = 0;
+  uint32_t chunk = 256;
+  uint64_t round_max = 1ull << 26;
+  // timing
+  bool timing = false;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  oi_timing tm{};
+};
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// Stage-1 table (Sec. 3.1)
+// ---------------------------------------------------------------------------
+struct HostQuery {
+  uint32_t qid = 0;
+  std::vector<int32_t> S;  // sorted, unique
+  int64_t l = 0;
+  double beta0 = 0.0;
+  std::vector<int32_t> v;
+  std::vector<double> P, cdf;
+  std::vector<uint64_t> thr;
+  std::vector<int64_t> se_off, se;  // S-edges into each entry, ascending edge id
+  std::vector<int32_t> shash;
+  uint32_t smask = 0;
+  DevBuf d_cdf, d_tab, d_shash;
+  oi::QueryDev dev{};
+};
+
+oi_status build_table(const oi_graph* g, const int32_t* seeds, int64_t k, HostQuery& Q) {
+  if (k <= 0 || !seeds) return fail(OI_EINVAL, "empty seed set");
+  Q.S.assign(seeds, seeds + k);
+  for (int32_t s : Q.S)
+    if (s < 0 || s >= g->n) return fail(OI_ERANGE, "seed id outside [0, n)");
+  std::sort(Q.S.begin(), Q.S.end());
+  Q.S.erase(std::unique(Q.S.begin(), Q.S.end()), Q.S.end());
+  auto inS = [&](int32_t x) { return std::binary_search(Q.S.begin(), Q.S.end(), x); };
+  // N^out_S with the edge ids that reach each neighbour
+  std::vector<std::pair<int32_t, int64_t>> ve;
+  for (int32_t u : Q.S)
+    for (int64_t e = g->row_ptr[u]; e < g->row_ptr[u + 1]; ++e)
+      if (!inS(g->col[e])) ve.emplace_back(g->col[e], e);
+  std::sort(ve.begin(), ve.end());
+  Q.v.clear();
+  Q.P.clear();
+  Q.se_off.clear();
+  Q.se.resize(ve.size());
+  for (size_t i = 0; i < ve.size(); ++i) {
+    if (i == 0 || ve[i].first != ve[i - 1].first) {
+      Q.v.push_back(ve[i].first);
+      Q.se_off.push_back((int64_t)i);
+    }
+    Q.se[i] = ve[i].second;
+  }
+  Q.l = (int64_t)Q.v.size();
+  Q.se_off.push_back((int64_t)ve.size());
+  if (Q.l >= (1ll << 31)) return fail(OI_ERANGE, "Stage-1 table too large");
+  // Eq. psv: P_{S,v} = 1 - prod (1 - w(u, v)), product in ascending edge id
+  Q.P.resize(Q.l);
+  Q.thr.resize(Q.l);
+  for (int64_t j = 0; j < Q.l; ++j) {
+    double prod = 1.0;
+    for (int64_t a = Q.se_off[j]; a < Q.se_off[j + 1]; ++a) prod = prod * (1.0 - (double)g->p[Q.se[a]]);
+    Q.P[j] = 1.0 - prod;
+    Q.thr[j] = (uint64_t)(Q.P[j] * 4294967296.0);
+  }
+  // Eq. pai / zerop: Pr[A_j] = P_j * prod_{i<j}(1 - P_i), CDF and beta_0
+  Q.cdf.assign(Q.l + 1, 0.0);
+  double rest = 1.0;
+  for (int64_t j = 0; j < Q.l; ++j) {
+    const double pa = rest * Q.P[j];
+    Q.cdf[j + 1] = Q.cdf[j] + pa;
+    rest = rest * (1.0 - Q.P[j]);
+  }
+  Q.beta0 = Q.cdf[Q.l];
+  // open-addressing set of S for the device
+  uint32_t cap = 2;
+  while (cap < 2 * Q.S.size()) cap <<= 1;
+  Q.smask = cap - 1;
+  Q.shash.assign(cap, -1);
+  for (int32_t s : Q.S) {
+    uint32_t h = oi::mix32((uint32_t)s) & Q.smask;
+    while (Q.shash[h] >= 0) h = (h + 1) & Q.smask;
+    Q.shash[h] = s;
+  }
+  return OI_OK;
+}
+
+oi_status upload_query(oi_graph* g, HostQuery& Q) {
+  const int64_t ng = (Q.l + 3) / 4;
+  std::vector<oi::TabGroup> tab((size_t)std::max<int64_t>(ng, 1));
+  std::memset(tab.data(), 0, tab.size() * sizeof(oi::TabGroup));
+  for (int64_t j = 0; j < Q.l; ++j) {
+    tab[j >> 2].v[j & 3] = Q.v[j];
+    tab[j >> 2].thr[j & 3] = Q.thr[j];
+  }
+  HIP_TRY(Q.d_tab.ensure(tab.size() * sizeof(oi::TabGroup)));
+  HIP_TRY(Q.d_cdf.ensure((size_t)(Q.l + 1) * sizeof(double)));
+  HIP_TRY(Q.d_shash.ensure(Q.shash.size() * sizeof(int32_t)));
+  HIP_TRY(hipMemcpy(Q.d_tab.p, tab.data(), tab.size() * sizeof(oi::TabGroup), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(Q.d_cdf.p, Q.cdf.data(), (size_t)(Q.l + 1) * sizeof(double), hipMemcpyHostToDevice));
+  HIP_TRY(hipMemcpy(Q.d_shash.p, Q.shash.data(), Q.shash.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+  Q.dev.cdf = Q.d_cdf.as<double>();
+  Q.dev.tab = Q.d_tab.as<oi::TabGroup>();
+  Q.dev.shash = Q.d_shash.as<int32_t>();
+  Q.dev.l = Q.l;
+  Q.dev.smask = Q.smask;
+  Q.dev.k = (int32_t)Q.S.size();
+  Q.dev.s0 = Q.S.size() == 1 ? Q.S[0] : -1;
+  Q.dev.qid = Q.qid;
+  Q.dev.beta0 = Q.beta0;
+  return OI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// sampling launches
+// ---------------------------------------------------------------------------
+struct SegReq {
+  uint32_t q;
+  uint32_t stream;
+  uint64_t first;
+  uint64_t count;
+  uint64_t out_off;
+};
+
+struct BwdBufs {
+  const uint32_t* y_in = nullptr;
+  unsigned long long *live = nullptr, *dead = nullptr, *tab = nullptr;
+};
+
+oi_status ensure_large_pool(oi_graph* g) {
+  if (g->large_blocks > 0) return OI_OK;
+  const int64_t words = (g->n + 31) / 32;
+  const double per = (double)words * 4.0 + (double)g->n * 4.0;
+  size_t freeb = 0, totalb = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+  double budget = std::min(16.0 * (1ull << 30), 0.25 * (double)freeb);
+  int blocks = (int)std::min<double>(1024.0, std::floor(budget / per));
+  if (blocks < 1) return fail(OI_ENOMEM, "no room for a large-cascade workspace");
+  blocks = std::min(blocks, 4 * g->cus);
+  HIP_TRY(g->d_bits.ensure((size_t)blocks * (size_t)words * 4));
+  HIP_TRY(g->d_queue.ensure((size_t)blocks * (size_t)g->n * 4));
+  HIP_TRY(hipMemsetAsync(g->d_bits.p, 0, (size_t)blocks * (size_t)words * 4, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  g->large_blocks = blocks;
+  return OI_OK;
+}
+
+// Runs the small- and large-cascade kernels over `segs`.  Y goes to y_dev
+// (indexed by out_off) unless bwd; per-segment sums come back in sums.
+oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, const std::vector<SegReq>& segs,
+                      uint32_t seed, uint32_t* y_dev, uint64_t* e_dev, std::vector<unsigned long long>& sums,
+                      const BwdBufs* bwd, int* rounds) {
+  sums.assign(2 * segs.size(), 0ull);
+  uint64_t total = 0;
+  std::vector<oi::Segment> ds(segs.size());
+  for (size_t i = 0; i < segs.size(); ++i) {
+    ds[i].q = segs[i].q;
+    ds[i].stream = segs[i].stream;
+    ds[i].first = segs[i].first;
+    ds[i].count = segs[i].count;
+    ds[i].out_off = segs[i].out_off;
+    ds[i].flat0 = total;
+    if (segs[i].first + segs[i].count > kMaxSample) return fail(OI_ERANGE, "sample index beyond 2^59");
+    total += segs[i].count;
+  }
+  if (total == 0) return OI_OK;
+  if (total > (1ull << 32)) return fail(OI_ERANGE, "too many samples in one launch");
+  OI_TRY(ensure_large_pool(g));
+  std::vector<oi::QueryDev> qd(qs.size());
+  for (size_t i = 0; i < qs.size(); ++i) qd[i] = qs[i]->dev;
+  HIP_TRY(g->d_segs.ensure(ds.size() * sizeof(oi::Segment)));
+  HIP_TRY(g->d_qs.ensure(qd.size() * sizeof(oi::QueryDev)));
+  HIP_TRY(g->d_sums.ensure(sums.size() * sizeof(unsigned long long)));
+  HIP_TRY(g->d_def.ensure(total * sizeof(unsigned long long)));
+  HIP_TRY(g->d_ctl.ensure(64));
+  HIP_TRY(hipMemcpyAsync(g->d_segs.p, ds.data(), ds.size() * sizeof(oi::Segment), hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipMemcpyAsync(g->d_qs.p, qd.data(), qd.size() * sizeof(oi::QueryDev), hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipMemsetAsync(g->d_sums.p, 0, sums.size() * sizeof(unsigned long long), g->stream));
+  HIP_TRY(hipMemsetAsync(g->d_ctl.p, 0, 64, g->stream));
+
+  oi::SampleLaunch A{};
+  A.n = g->n;
+  A.row_ptr = g->d_row_ptr.as<int64_t>();
+  A.eg = g->d_eg.as<oi::EdgeGroup>();
+  A.qs = g->d_qs.as<oi::QueryDev>();
+  A.segs = g->d_segs.as<oi::Segment>();
+  A.nseg = (int32_t)ds.size();
+  A.total = total;
+  A.seed = seed;
+  A.y_out = y_dev;
+  A.e_out = e_dev;
+  A.seg_sums = g->d_sums.as<unsigned long long>();
+  unsigned long long* ctl = g->d_ctl.as<unsigned long long>();
+  A.counter = ctl;
+  A.ndeferred = reinterpret_cast<unsigned int*>(ctl + 1);
+  A.err = reinterpret_cast<unsigned int*>(ctl + 2);
+  A.large_sums = ctl + 3;
+  A.deferred = g->d_def.as<unsigned long long>();
+  A.chunk = g->chunk;
+  A.bits = g->d_bits.as<uint32_t>();
+  A.queue = g->d_queue.as<int32_t>();
+  A.bits_words = (g->n + 31) / 32;
+  const bool is_bwd = bwd != nullptr;
+  if (is_bwd) {
+    A.y_in = bwd->y_in;
+    A.acc_live = bwd->live;
+    A.acc_dead = bwd->dead;
+    A.acc_tab = bwd->tab;
+  }
+  int bpc = 0;
+  HIP_TRY(oi::small_occupancy(g->variant, is_bwd, &bpc));
+  if (bpc < 1) bpc = 1;
+  uint64_t want = (total + 63) / 64;  // never more waves than needed
+  int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want + 3) / 4));
+  if (g->timing) HIP_TRY(hipEventRecord(g->ev[0], g->stream));
+  HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, g->stream));
+  if (g->timing) HIP_TRY(hipEventRecord(g->ev[1], g->stream));
+  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
+  if (g->timing) HIP_TRY(hipEventRecord(g->ev[2], g->stream));
+  unsigned long long hctl[5] = {0, 0, 0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(sums.data(), g->d_sums.p, sums.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         g->stream));
+  HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  const unsigned int ndef = (unsigned int)(hctl[1] & 0xffffffffull);
+  const unsigned int err = (unsigned int)(hctl[2] & 0xffffffffull);
+  if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
+  if (rounds) ++*rounds;
+  if (g->timing) {
+    float a = 0, b = 0;
+    HIP_TRY(hipEventElapsedTime(&a, g->ev[0], g->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&b, g->ev[1], g->ev[2]));
+    g->tm.small_ms += a;
+    g->tm.large_ms += b;
+    g->tm.small_launches += 1;
+    g->tm.large_launches += 1;
+    g->tm.samples += total;
+    g->tm.deferred += ndef;
+    for (size_t i = 0; i < segs.size(); ++i) {
+      g->tm.sum_y += sums[2 * i];
+      g->tm.edges += sums[2 * i + 1];
+    }
+    g->tm.large_sum_y += hctl[3];
+    g->tm.large_edges += hctl[4];
+  }
+  return OI_OK;
+}
+
+// ---------------------------------------------------------------------------
+// GSRA / RSA controller (Algs. 2, 3) with SOIEA / SIEA transforms (Algs. 4, 5)
+// ---------------------------------------------------------------------------
+typedef unsigned __int128 u128;
+
+// Upsilon = (1 + eps) c(eps', delta) (b - a) with
+// eps' = eps (1 - eps b / ((2 + 2/3 eps) ln(2/delta) (b - a))) and
+// c(x, delta) = (2 + 2/3 x) ln(2/delta) / x^2 (Alg. 2 line 2, Table 1).
+double stop_threshold(double eps, double delta, double a, double b) {
+  const double L = std::log(2.0 / delta);
+  const double epsp = eps * (1.0 - (eps * b) / ((2.0 + (2.0 / 3.0) * eps) * L * (b - a)));
+  const double c = (2.0 + (2.0 / 3.0) * epsp) * L / (epsp * epsp);
+  return (1.0 + eps) * c * (b - a);
+}
+
+enum Phase { P_DONE = 0, P_STEP1 = 1, P_STEP2 = 2, P_STEP3 = 3 };
+
+struct Rsa {
+  HostQuery* Q = nullptr;
+  int qi = 0;
+  double eps = 0, delta = 0, a = 0, b = 0, scale = 1, offset = 0;
+  int mode = 0;
+  Phase phase = P_DONE;
+  bool gsra_only = false;
+  double e1 = 0, d1 = 0, ups1 = 0;  // the GSRA run on stream X (step 1 or the only step)
+  // stream X
+  uint64_t nx = 0, hx = 0;
+  std::vector<unsigned long long> xchunks;  // sums of kChunk consecutive Y of X
+  double ups2 = 0;
+  // stream X'
+  uint64_t pairs_done = 0;
+  u128 D = 0;
+  // results
+  oi_result r{};
+  double sumx(uint64_t h, uint64_t T) const { return scale * (double)h + offset * (double)T; }
+  bool crossed(uint64_t h, uint64_t T) const { return !(sumx(h, T) < ups1); }
+};
+
+void finish_result(Rsa& R) {
+  R.r.mu = R.r.T ? R.sumx(R.r.hT, R.r.T) / (double)R.r.T : R.a;
+  if (R.mode == OI_MODE_SOIEA) {
+    R.r.oi = R.Q->beta0 * R.r.mu;
+    R.r.is = R.r.oi + (double)R.Q->S.size();
+  } else {
+    R.r.is = R.r.mu;
+    R.r.oi = R.r.is - (double)R.Q->S.size();
+  }
+  R.phase = P_DONE;
+}
+
+// Step 2 / step 3 set-up once step 1 has its estimate (Alg. 3 lines 4-9).
+oi_status after_step1(Rsa& R) {
+  if (R.gsra_only) {  // Alg. 3 lines 1-2: the GSRA estimate is the answer
+    R.r.T = R.r.T1;
+    R.r.hT = R.r.h1;
+    finish_result(R);
+    return OI_OK;
+  }
+  R.r.mu1 = R.r.T1 ? R.sumx(R.r.h1, R.r.T1) / (double)R.r.T1 : R.a;
+  const double se = std::sqrt(R.eps);
+  const double L = std::log(2.0 / R.delta);
+  const double ups = stop_threshold(R.eps, R.delta, R.a, R.b);
+  const double ups2 = 2.0 * (1.0 + se) / (1.0 - se) * (1.0 + std::log(1.5) / L) * ups;
+  const double ns = std::ceil(ups2 * R.eps / R.r.mu1);
+  if (!(ns < 4.0e18)) return fail(OI_ERANGE, "N_sigma out of range");
+  R.r.nsigma = ns < 1.0 ? 1 : (uint64_t)ns;
+  R.ups2 = ups2;
+  R.phase = P_STEP2;
+  return OI_OK;
+}
+
+// Sum of Y over X_1..X_T for T <= nx, from chunk sums plus a recomputed tail.
+oi_status prefix_sum_x(oi_graph* g, Rsa& R, uint64_t T, uint32_t seed, uint64_t* out, int* rounds) {
+  const uint64_t full = T / kChunk;
+  uint64_t h = 0;
+  for (uint64_t c = 0; c < full; ++c) h += R.xchunks[c];
+  const uint64_t rest = T - full * kChunk;
+  if (rest) {
+    std::vector<const HostQuery*> qv{R.Q};
+    std::vector<SegReq> seg{{0, 0, full * kChunk, rest, 0}};
+    std::vector<unsigned long long> sums;
+    DevBuf tmp;  // not the round buffer: other queries' Y of this round may still be unread there
+    HIP_TRY(tmp.ensure(kChunk * 4));
+    OI_TRY(run_sampler(g, qv, seg, seed, tmp.as<uint32_t>(), nullptr, sums, nullptr, rounds));
+    h += sums[0];
+  }
+  *out = h;
+  return OI_OK;
+}
+
+oi_status set_step3(oi_graph* g, Rsa& R, uint32_t seed, int* rounds) {
+  R.r.D_lo = (uint64_t)R.D;
+  R.r.D_hi = (uint64_t)(R.D >> 64);
+  const double ups2 = R.ups2;
+  const double Delta = R.scale * R.scale * (double)R.D / 2.0;
+  const double rho1 = Delta / (double)R.r.nsigma;
+  const double rho2 = R.eps * R.r.mu1 * (R.b - R.a);
+  const double rho = rho1 > rho2 ? rho1 : rho2;
+  const double tt = std::ceil(ups2 * rho / (R.r.mu1 * R.r.mu1 * (R.b - R.a)));
+  if (!(tt < 4.0e18)) return fail(OI_ERANGE, "T out of range");
+  R.r.T = tt < 1.0 ? 1 : (uint64_t)tt;
+  if (R.r.T <= R.nx) {
+    OI_TRY(prefix_sum_x(g, R, R.r.T, seed, &R.r.hT, rounds));
+    finish_result(R);
+  } else {
+    R.phase = P_STEP3;
+  }
+  return OI_OK;
+}
+
+// Scan a round's chunk sums for the first index where the GSRA rule stops.
+oi_status scan_crossing(oi_graph* g, Rsa& R, const std::vector<unsigned long long>& ch, uint64_t first,
+                        uint64_t count, const uint32_t* ydev, bool* found) {
+  uint64_t h = R.hx, T = first;  // totals before this round
+  *found = false;
+  for (size_t c = 0; c < ch.size(); ++c) {
+    const uint64_t n = std::min<uint64_t>(kChunk, count - (uint64_t)c * kChunk);
+    if (R.crossed(h + ch[c], T + n)) {
+      std::vector<uint32_t> y(n);
+      HIP_TRY(hipMemcpy(y.data(), ydev + (size_t)c * kChunk, n * 4, hipMemcpyDeviceToHost));
+      for (uint64_t i = 0; i < n; ++i) {
+        h += y[i];
+        T += 1;
+        if (R.crossed(h, T)) {
+          R.r.T1 = T;
+          R.r.h1 = h;
+          *found = true;
+          return OI_OK;
+        }
+      }
+      return fail(OI_ESTATE, "chunk sum and per-sample crossing disagree");
+    }
+    h += ch[c];
+    T += n;
+  }
+  return OI_OK;
+}
+
+uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
+
+// Drive every query in `rs` to completion.  Each round makes one sampling
+// launch that serves all unfinished queries; segments start at multiples of
+// kChunk in the round buffer so one chunk-sum launch covers all of them.
+oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
+  HIP_TRY(g->d_y.ensure((size_t)g->round_max * 4));
+  const uint64_t cap = g->round_max;
+  for (int guard = 0;; ++guard) {
+    if (guard > 10000000) return fail(OI_ESTATE, "stopping rule did not converge");
+    std::vector<int> owner;
+    std::vector<uint64_t> want;
+    for (size_t i = 0; i < rs.size(); ++i) {
+      Rsa& R = rs[i];
+      if (R.phase == P_DONE) continue;
+      uint64_t need = 0;
+      if (R.phase == P_STEP1) {
+        double remaining = 65536.0;
+        if (R.nx > 0) {
+          const double cur = R.sumx(R.hx, R.nx);
+          remaining = (R.ups1 - cur) / (cur / (double)R.nx) * 1.02 + (double)kChunk;
+        }
+        need = (uint64_t)std::min<double>(std::max<double>(remaining, (double)kChunk), (double)cap);
+        need = round_up(need, kChunk);
+      } else if (R.phase == P_STEP2) {
+        need = std::min<uint64_t>(2 * (R.r.nsigma - R.pairs_done), cap);
+      } else {
+        need = R.r.T - R.nx;
+        if (need > cap) need = cap;
+      }
+      want.push_back(need);
+      owner.push_back((int)i);
+    }
+    if (owner.empty()) break;
+    // share the round buffer: at most an equal share each, whole chunks
+    // (pairs for X'), and never past the end of the buffer
+    const uint64_t share = std::max<uint64_t>(kChunk, cap / owner.size() / kChunk * kChunk);
+    std::vector<const HostQuery*> qv;
+    std::vector<SegReq> segs;
+    std::vector<int> seg_owner;
+    uint64_t off = 0;
+    for (size_t j = 0; j < owner.size(); ++j) {
+      Rsa& R = rs[owner[j]];
+      uint64_t w = want[j];
+      if (w > share) w = R.phase == P_STEP2 ? (share & ~1ull) : share;
+      if (off + w > cap) {
+        const uint64_t room = cap - off;
+        if (room < kChunk) break;
+        w = R.phase == P_STEP2 ? (room & ~1ull) : (R.phase == P_STEP1 ? room / kChunk * kChunk : std::min(w, room / kChunk * kChunk));
+        if (w == 0) break;
+      }
+      SegReq sreq{};
+      sreq.q = (uint32_t)qv.size();
+      sreq.stream = R.phase == P_STEP2 ? 1u : 0u;
+      sreq.first = R.phase == P_STEP2 ? 2 * R.pairs_done : R.nx;
+      sreq.count = w;
+      sreq.out_off = off;
+      qv.push_back(R.Q);
+      segs.push_back(sreq);
+      seg_owner.push_back(owner[j]);
+      off = round_up(off + w, kChunk);
+    }
+    std::vector<unsigned long long> sums;
+    int launches = 0;
+    OI_TRY(run_sampler(g, qv, segs, seed, g->d_y.as<uint32_t>(), nullptr, sums, nullptr, &launches));
+    uint32_t* ydev = g->d_y.as<uint32_t>();
+    // chunk sums over the whole round buffer (used by X segments)
+    bool any_x = false;
+    for (const SegReq& sq : segs) any_x |= sq.stream == 0;
+    std::vector<unsigned long long> ch;
+    if (any_x) {
+      const uint64_t nch = (off + kChunk - 1) / kChunk;
+      HIP_TRY(g->d_chunks.ensure(nch * 8));
+      HIP_TRY(oi::launch_chunk_sums(ydev, off, kChunk, g->d_chunks.as<unsigned long long>(), g->stream));
+      ch.resize(nch);
+      HIP_TRY(hipMemcpyAsync(ch.data(), g->d_chunks.p, nch * 8, hipMemcpyDeviceToHost, g->stream));
+    }
+    // squared paired differences for X' segments
+    std::vector<unsigned char> pbuf;
+    std::vector<size_t> pair_seg;
+    uint64_t ptotal = 0;
+    for (size_t i = 0; i < segs.size(); ++i) {
+      if (segs[i].stream != 1) continue;
+      struct {
+        uint64_t out_off, npairs, flat0;
+        uint32_t acc, pad;
+      } ps{segs[i].out_off, segs[i].count / 2, ptotal, (uint32_t)pair_seg.size(), 0};
+      static_assert(sizeof(ps) == 32, "PairSeg layout");
+      if (oi::pair_seg_size() != sizeof(ps)) return fail(OI_ESTATE, "PairSeg layout mismatch");
+      const unsigned char* pb = reinterpret_cast<const unsigned char*>(&ps);
+      pbuf.insert(pbuf.end(), pb, pb + sizeof(ps));
+      ptotal += segs[i].count / 2;
+      pair_seg.push_back(i);
+    }
+    std::vector<unsigned long long> pacc(2 * pair_seg.size());
+    if (!pair_seg.empty()) {
+      HIP_TRY(g->d_pairs.ensure(pbuf.size()));
+      HIP_TRY(g->d_pacc.ensure(pacc.size() * 8));
+      HIP_TRY(hipMemcpyAsync(g->d_pairs.p, pbuf.data(), pbuf.size(), hipMemcpyHostToDevice, g->stream));
+      HIP_TRY(hipMemsetAsync(g->d_pacc.p, 0, pacc.size() * 8, g->stream));
+      HIP_TRY(oi::launch_pair_sq(ydev, g->d_pairs.p, (int32_t)pair_seg.size(), ptotal,
+                                 g->d_pacc.as<unsigned long long>(), g->stream));
+      HIP_TRY(hipMemcpyAsync(pacc.data(), g->d_pacc.p, pacc.size() * 8, hipMemcpyDeviceToHost, g->stream));
+    }
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    size_t pj = 0;
+    for (size_t i = 0; i < segs.size(); ++i) {
+      Rsa& R = rs[seg_owner[i]];
+      const SegReq& sq = segs[i];
+      R.r.rounds += 1;
+      R.r.sum_y += sums[2 * i];
+      R.r.edges_examined += sums[2 * i + 1];
+      if (sq.stream == 1) {
+        R.D += ((u128)pacc[2 * pj + 1] << 64) | (u128)pacc[2 * pj];
+        ++pj;
+        R.pairs_done += sq.count / 2;
+        R.r.samples_xp += sq.count;
+        if (R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
+        continue;
+      }
+      const uint64_t c0 = sq.out_off / kChunk, nc = (sq.count + kChunk - 1) / kChunk;
+      std::vector<unsigned long long> mine(ch.begin() + (long)c0, ch.begin() + (long)(c0 + nc));
+      if (R.phase == P_STEP1) {
+        bool found = false;
+        OI_TRY(scan_crossing(g, R, mine, R.nx, sq.count, ydev + sq.out_off, &found));
+        R.xchunks.insert(R.xchunks.end(), mine.begin(), mine.end());
+        R.nx += sq.count;
+        R.hx += sums[2 * i];
+        R.r.samples_x += sq.count;
+        if (found) {
+          OI_TRY(after_step1(R));
+          if (R.phase == P_STEP2 && R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
+        }
+      } else {  // step 3 extends stream X up to T
+        R.xchunks.insert(R.xchunks.end(), mine.begin(), mine.end());
+        R.nx += sq.count;
+        R.hx += sums[2 * i];
+        R.r.samples_x += sq.count;
+        if (R.nx == R.r.T) {
+          R.r.hT = R.hx;
+          finish_result(R);
+        }
+      }
+    }
+  }
+  return OI_OK;
+}
+
+oi_status init_rsa(Rsa& R, HostQuery* Q, int64_t n, double eps, double delta, int mode) {
+  R.Q = Q;
+  R.eps = eps;
+  R.delta = delta;
+  R.mode = mode;
+  R.r = oi_result{};
+  R.r.beta0 = Q->beta0;
+  R.r.k = (int64_t)Q->S.size();
+  R.r.l = Q->l;
+  const double kd = (double)Q->S.size();
+  const double nk = (double)(n - (int64_t)Q->S.size());
+  if (Q->beta0 == 0.0) {  // no out-neighbour outside S: OI = 0, IS = |S|
+    R.r.oi = 0.0;
+    R.r.is = kd;
+    R.phase = P_DONE;
+    return OI_OK;
+  }
+  if (mode == OI_MODE_SOIEA) {
+    R.a = 1.0;
+    R.b = nk;
+    R.scale = 1.0;
+    R.offset = 0.0;
+  } else {
+    R.a = kd + Q->beta0;
+    R.b = kd + Q->beta0 * nk;
+    R.scale = Q->beta0;
+    R.offset = kd;
+  }
+  if (!(R.b > R.a)) {  // Y is always 1 (n - |S| = 1): the mean is the lower bound
+    R.r.early = 1;
+    R.r.mu = R.a;
+    if (mode == OI_MODE_SOIEA) {
+      R.r.oi = Q->beta0 * R.a;
+      R.r.is = R.r.oi + kd;
+    } else {
+      R.r.is = R.a;
+      R.r.oi = R.r.is - kd;
+    }
+    R.phase = P_DONE;
+    return OI_OK;
+  }
+  R.gsra_only = eps >= 0.25;
+  R.r.gsra_only = R.gsra_only ? 1 : 0;
+  R.e1 = R.gsra_only ? eps : std::sqrt(eps);
+  R.d1 = R.gsra_only ? delta : delta / 3.0;
+  if (R.b - R.a < R.e1 * R.b) {  // Alg. 2 line 1
+    R.r.early = 1;
+    R.r.T1 = 0;
+    R.r.h1 = 0;
+    return after_step1(R);
+  }
+  R.ups1 = stop_threshold(R.e1, R.d1, R.a, R.b);
+  R.phase = P_STEP1;
+  return OI_OK;
+}
+
+oi_status check_eps_delta(double eps, double delta, int mode) {
+  if (!(eps > 0.0 && eps < 1.0)) return fail(OI_EINVAL, "eps must lie in (0, 1)");
+  if (!(delta > 0.0 && delta < 0.5)) return fail(OI_EINVAL, "delta must lie in (0, 1/2)");
+  if (mode != OI_MODE_SOIEA && mode != OI_MODE_SIEA) return fail(OI_EINVAL, "unknown mode");
+  return OI_OK;
+}
+
+oi_status upload_graph(oi_graph* g) {
+  g->ngroups = (g->m + 3) / 4;
+  std::vector<oi::EdgeGroup> eg((size_t)std::max<int64_t>(g->ngroups, 1));
+  std::memset(eg.data(), 0, eg.size() * sizeof(oi::EdgeGroup));
+  for (int64_t e = 0; e < g->m; ++e) {
+    eg[e >> 2].v[e & 3] = g->col[e];
+    eg[e >> 2].p[e & 3] = g->p[e];
+  }
+  HIP_TRY(g->d_eg.ensure(eg.size() * sizeof(oi::EdgeGroup)));
+  HIP_TRY(hipMemcpy(g->d_eg.p, eg.data(), eg.size() * sizeof(oi::EdgeGroup), hipMemcpyHostToDevice));
+  return OI_OK;
+}
+
+oi_status validate_probs(const std::vector<float>& p) {
+  for (float x : p)
+    if (!(x >= 0.0f && x <= 1.0f)) return fail(OI_EINVAL, "edge probability outside [0, 1]");
+  return OI_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char* oi_last_error(void) { return g_err.c_str(); }
+
+oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const float* p,
+                          int device_ptrs, void* hip_stream, oi_graph** out) {
+  if (!out) return fail(OI_EINVAL, "out is null");
+  *out = nullptr;
+  if (n <= 0 || n >= (1ll << 31) || m < 0) return fail(OI_EINVAL, "need 0 < n < 2^31 and m >= 0");
+  if (!row_ptr || (m > 0 && (!col || !p))) return fail(OI_EINVAL, "null CSR array");
+  std::unique_ptr<oi_graph> g(new oi_graph());
+  g->n = n;
+  g->m = m;
+  g->stream = (hipStream_t)hip_stream;
+  g->row_ptr.resize((size_t)n + 1);
+  g->col.resize((size_t)m);
+  g->p.resize((size_t)m);
+  if (device_ptrs) {
+    HIP_TRY(hipMemcpy(g->row_ptr.data(), row_ptr, ((size_t)n + 1) * 8, hipMemcpyDeviceToHost));
+    if (m) {
+      HIP_TRY(hipMemcpy(g->col.data(), col, (size_t)m * 4, hipMemcpyDeviceToHost));
+      HIP_TRY(hipMemcpy(g->p.data(), p, (size_t)m * 4, hipMemcpyDeviceToHost));
+    }
+  } else {
+    std::memcpy(g->row_ptr.data(), row_ptr, ((size_t)n + 1) * 8);
+    if (m) {
+      std::memcpy(g->col.data(), col, (size_t)m * 4);
+      std::memcpy(g->p.data(), p, (size_t)m * 4);
+    }
+  }
+  if (g->row_ptr[0] != 0 || g->row_ptr[n] != m) return fail(OI_EINVAL, "row_ptr[0] must be 0 and row_ptr[n] = m");
+  for (int64_t u = 0; u < n; ++u) {
+    const int64_t d = g->row_ptr[u + 1] - g->row_ptr[u];
+    if (d < 0) return fail(OI_EINVAL, "row_ptr must be non-decreasing");
+    if (d >= (1ll << 29)) return fail(OI_ERANGE, "out-degree must stay below 2^29");
+  }
+  for (int64_t e = 0; e < m; ++e)
+    if (g->col[e] < 0 || g->col[e] >= n) return fail(OI_EINVAL, "col entry outside [0, n)");
+  OI_TRY(validate_probs(g->p));
+  HIP_TRY(hipGetDevice(&g->device));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, g->device));
+  g->cus = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  HIP_TRY(g->d_row_ptr.ensure(((size_t)n + 1) * 8));
+  HIP_TRY(hipMemcpy(g->d_row_ptr.p, g->row_ptr.data(), ((size_t)n + 1) * 8, hipMemcpyHostToDevice));
+  OI_TRY(upload_graph(g.get()));
+  for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&g->ev[i]));
+  *out = g.release();
+  return OI_OK;
+}
+
+oi_status oi_graph_set_probs(oi_graph* g, const float* p, int device_ptr) {
+  if (!g || (g->m > 0 && !p)) return fail(OI_EINVAL, "null argument");
+  std::vector<float> np((size_t)g->m);
+  if (g->m) {
+    if (device_ptr)
+      HIP_TRY(hipMemcpy(np.data(), p, (size_t)g->m * 4, hipMemcpyDeviceToHost));
+    else
+      std::memcpy(np.data(), p, (size_t)g->m * 4);
+  }
+  OI_TRY(validate_probs(np));
+  g->p.swap(np);
+  return upload_graph(g);
+}
+
+oi_status oi_set_stream(oi_graph* g, void* hip_stream) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  g->stream = (hipStream_t)hip_stream;
+  return OI_OK;
+}
+
+void oi_graph_destroy(oi_graph* g) {
+  if (!g) return;
+  (void)hipStreamSynchronize(g->stream);
+  for (int i = 0; i < 3; ++i)
+    if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
+  delete g;
+}
+
+oi_status oi_stage1_table(oi_graph* g, const int32_t* seeds, int64_t k, int64_t cap, int64_t* l_out, double* beta0,
+                          int32_t* v, double* P, double* cdf, uint64_t* thr) {
+  if (!g || !l_out || !beta0) return fail(OI_EINVAL, "null argument");
+  HostQuery Q;
+  OI_TRY(build_table(g, seeds, k, Q));
+  *l_out = Q.l;
+  *beta0 = Q.beta0;
+  if (Q.l <= cap) {
+    if (v) std::copy(Q.v.begin(), Q.v.end(), v);
+    if (P) std::copy(Q.P.begin(), Q.P.end(), P);
+    if (cdf) std::copy(Q.cdf.begin(), Q.cdf.end(), cdf);
+    if (thr) std::copy(Q.thr.begin(), Q.thr.end(), thr);
+  }
+  return OI_OK;
+}
+
+oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
+                          uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out,
+                          oi_result* sums) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (stream != 0 && stream != 1) return fail(OI_EINVAL, "stream must be 0 or 1");
+  if (first + count < first || first + count > kMaxSample) return fail(OI_ERANGE, "sample range beyond 2^59");
+  if (e_out && !y_out) return fail(OI_EINVAL, "e_out needs y_out");
+  HostQuery Q;
+  Q.qid = query_id;
+  OI_TRY(build_table(g, seeds, k, Q));
+  oi_result r{};
+  r.beta0 = Q.beta0;
+  r.k = (int64_t)Q.S.size();
+  r.l = Q.l;
+  if (Q.beta0 > 0.0 && count > 0) {
+    OI_TRY(upload_query(g, Q));
+    uint32_t* ybuf = y_out;
+    if (!ybuf) {
+      HIP_TRY(g->d_y.ensure((size_t)std::min<uint64_t>(count, g->round_max) * 4));
+      ybuf = g->d_y.as<uint32_t>();
+    }
+    std::vector<const HostQuery*> qv{&Q};
+    for (uint64_t done = 0; done < count;) {
+      const uint64_t c = std::min<uint64_t>(count - done, g->round_max);
+      std::vector<SegReq> seg{{0, (uint32_t)stream, first + done, c, y_out ? done : 0}};
+      std::vector<unsigned long long> s;
+      OI_TRY(run_sampler(g, qv, seg, run_seed, ybuf, e_out ? e_out : nullptr, s, nullptr, &r.rounds));
+      r.sum_y += s[0];
+      r.edges_examined += s[1];
+      done += c;
+    }
+    if (stream == 0)
+      r.samples_x = count;
+    else
+      r.samples_xp = count;
+  }
+  if (sums) *sums = r;
+  return OI_OK;
+}
+
+oi_status oi_estimate(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, double eps, double delta,
+                      oi_mode mode, uint32_t run_seed, oi_result* out) {
+  const int64_t off[2] = {0, k};
+  return oi_estimate_batch(g, 1, off, seeds, &query_id, eps, delta, mode, run_seed, out);
+}
+
+oi_status oi_estimate_batch(oi_graph* g, int32_t nq, const int64_t* seed_off, const int32_t* seeds,
+                            const uint32_t* query_ids, double eps, double delta, oi_mode mode, uint32_t run_seed,
+                            oi_result* out) {
+  if (!g || !out || !seed_off || !query_ids || nq <= 0) return fail(OI_EINVAL, "null or empty argument");
+  OI_TRY(check_eps_delta(eps, delta, mode));
+  std::vector<std::unique_ptr<HostQuery>> qs((size_t)nq);
+  std::vector<Rsa> rs;
+  rs.reserve((size_t)nq);
+  for (int32_t q = 0; q < nq; ++q) {
+    out[q] = oi_result{};
+    qs[q].reset(new HostQuery());
+    qs[q]->qid = query_ids[q];
+    const int64_t k = seed_off[q + 1] - seed_off[q];
+    oi_status st = build_table(g, seeds + seed_off[q], k, *qs[q]);
+    if (st != OI_OK) {
+      if (nq == 1) return st;
+      out[q].status = st;
+      continue;
+    }
+    if (qs[q]->beta0 > 0.0) OI_TRY(upload_query(g, *qs[q]));
+    Rsa R;
+    R.qi = q;
+    OI_TRY(init_rsa(R, qs[q].get(), g->n, eps, delta, mode));
+    rs.push_back(std::move(R));
+  }
+  OI_TRY(rsa_drive(g, rs, run_seed));
+  for (Rsa& R : rs) out[R.qi] = R.r;
+  return OI_OK;
+}
+
+oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, uint64_t first,
+                      uint64_t count, uint32_t run_seed, const uint32_t* y_in, oi_param param, double grad_scale,
+                      float* grad_out) {
+  if (!g || !grad_out) return fail(OI_EINVAL, "null argument");
+  if (param != OI_PARAM_P && param != OI_PARAM_THETA) return fail(OI_EINVAL, "unknown parameterisation");
+  if (count == 0) return fail(OI_EINVAL, "count must be positive");
+  if (count > g->round_max) return fail(OI_ERANGE, "backward count above the round size");
+  if (first + count > kMaxSample) return fail(OI_ERANGE, "sample range beyond 2^59");
+  HostQuery Q;
+  Q.qid = query_id;
+  OI_TRY(build_table(g, seeds, k, Q));
+  HIP_TRY(hipMemsetAsync(grad_out, 0, (size_t)g->m * 4, g->stream));
+  if (Q.beta0 == 0.0) {
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    return OI_OK;
+  }
+  OI_TRY(upload_query(g, Q));
+  std::vector<const HostQuery*> qv{&Q};
+  DevBuf yb;
+  const uint32_t* y = y_in;
+  int rounds = 0;
+  if (!y) {
+    HIP_TRY(yb.ensure(count * 4));
+    std::vector<SegReq> seg{{0, 0, first, count, 0}};
+    std::vector<unsigned long long> s;
+    OI_TRY(run_sampler(g, qv, seg, run_seed, yb.as<uint32_t>(), nullptr, s, nullptr, &rounds));
+    y = yb.as<uint32_t>();
+  }
+  DevBuf acc, tab, seoff, se, P;
+  HIP_TRY(acc.ensure((size_t)std::max<int64_t>(g->m, 1) * 16));
+  HIP_TRY(tab.ensure((size_t)std::max<int64_t>(Q.l, 1) * 8));
+  HIP_TRY(hipMemsetAsync(acc.p, 0, (size_t)std::max<int64_t>(g->m, 1) * 16, g->stream));
+  HIP_TRY(hipMemsetAsync(tab.p, 0, (size_t)std::max<int64_t>(Q.l, 1) * 8, g->stream));
+  BwdBufs bb;
+  bb.y_in = y;
+  bb.live = acc.as<unsigned long long>();
+  bb.dead = acc.as<unsigned long long>() + std::max<int64_t>(g->m, 1);
+  bb.tab = tab.as<unsigned long long>();
+  std::vector<SegReq> seg{{0, 0, first, count, 0}};
+  std::vector<unsigned long long> s;
+  OI_TRY(run_sampler(g, qv, seg, run_seed, nullptr, nullptr, s, &bb, &rounds));
+  const unsigned long long sumY = s[0];
+  const double scale = grad_scale * Q.beta0 / (double)count;
+  const int theta = param == OI_PARAM_THETA ? 1 : 0;
+  HIP_TRY(oi::launch_bwd_edges(g->d_eg.as<oi::EdgeGroup>(), g->m, bb.live, bb.dead, scale, theta, grad_out,
+                               g->stream));
+  HIP_TRY(seoff.ensure(Q.se_off.size() * 8));
+  HIP_TRY(se.ensure(std::max<size_t>(Q.se.size(), 1) * 8));
+  HIP_TRY(P.ensure(std::max<size_t>(Q.P.size(), 1) * 8));
+  HIP_TRY(hipMemcpy(seoff.p, Q.se_off.data(), Q.se_off.size() * 8, hipMemcpyHostToDevice));
+  if (!Q.se.empty()) HIP_TRY(hipMemcpy(se.p, Q.se.data(), Q.se.size() * 8, hipMemcpyHostToDevice));
+  if (!Q.P.empty()) HIP_TRY(hipMemcpy(P.p, Q.P.data(), Q.P.size() * 8, hipMemcpyHostToDevice));
+  HIP_TRY(oi::launch_bwd_stage1(g->d_eg.as<oi::EdgeGroup>(), seoff.as<int64_t>(), se.as<int64_t>(), P.as<double>(),
+                                Q.l, bb.tab, sumY, scale, theta, grad_out, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  return OI_OK;
+}
+
+oi_status oi_timing_enable(oi_graph* g, int enable) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  g->timing = enable != 0;
+  g->tm = oi_timing{};
+  return OI_OK;
+}
+
+oi_status oi_timing_get(oi_graph* g, oi_timing* out) {
+  if (!g || !out) return fail(OI_EINVAL, "null argument");
+  *out = g->tm;
+  return OI_OK;
+}
+
+oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int64_t round_max) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (variant >= oi::num_small_variants()) return fail(OI_EINVAL, "unknown variant");
+  if (variant >= 0) g->variant = variant;
+  if (chunk > 0) g->chunk = (uint32_t)chunk;
+  if (round_max > 0) {
+    if (round_max % kChunk) return fail(OI_EINVAL, "round_max must be a multiple of 4096");
+    if (round_max > (1ll << 31)) return fail(OI_ERANGE, "round_max above 2^31");
+    g->round_max = (uint64_t)round_max;
+  }
+  return OI_OK;
+}
+
+int oi_num_variants(void) { return oi::num_small_variants(); }
+
+oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* ring_cap, int* rounds_per_pass) {
+  if (variant < 0 || variant >= oi::num_small_variants()) return fail(OI_EINVAL, "unknown variant");
+  int a, b, c, d;
+  oi::small_variant_info(variant, &a, &b, &c, &d);
+  if (slots_per_wave) *slots_per_wave = a;
+  if (hash_cap) *hash_cap = b;
+  if (ring_cap) *ring_cap = c;
+  if (rounds_per_pass) *rounds_per_pass = d;
+  return OI_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,97 @@
+// Device-side data layout shared by the HIP kernels and the host library code.
+// Internal to the library: the public boundary is include/oi.h.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace oi {
+
+// Out-edges in groups of four consecutive CSR edge ids (edge e lives in group
+// e/4, lane e%4).  One group is 32 bytes, so a sampler lane reads the targets
+// and probabilities of four edges with two 16-byte loads from one 64-byte
+// line, and the four coins of a group come from one Philox block.  Padding
+// entries past m have v = 0, p = 0 and are never inside a row range.
+struct alignas(32) EdgeGroup {
+  int32_t v[4];
+  float p[4];
+};
+
+// Stage-1 table entries in groups of four (entry j in group j/4): the
+// neighbour v_j and its coin threshold floor(P_{S,v_j} * 2^32), which may be
+// 2^32 when P = 1.  48 bytes per group.
+struct alignas(16) TabGroup {
+  int32_t v[4];
+  uint64_t thr[4];
+};
+
+// One seed set's read-only data.
+struct QueryDev {
+  const double* cdf;     // l+1 values, cdf[0] = 0, cdf[l] = beta_0
+  const TabGroup* tab;   // ceil(l/4) groups
+  const int32_t* shash;  // open-addressing set of S (capacity smask+1), -1 = empty
+  int64_t l;
+  uint32_t smask;
+  int32_t k;             // |S| after removing duplicates
+  int32_t s0;            // the seed when k == 1
+  uint32_t qid;          // Philox key word 0
+  double beta0;
+};
+
+// A contiguous range of samples of one query's stream.  Samples of all
+// segments of a launch are numbered by one flat index f; segment i covers
+// f in [flat0, flat0 + count), sample index s = first + (f - flat0), output
+// slot out_off + (f - flat0).
+struct Segment {
+  uint32_t q;
+  uint32_t stream;
+  uint64_t first;
+  uint64_t count;
+  uint64_t out_off;
+  uint64_t flat0;
+};
+
+struct SampleLaunch {
+  int64_t n;
+  const int64_t* row_ptr;
+  const EdgeGroup* eg;
+  const QueryDev* qs;
+  const Segment* segs;
+  int32_t nseg;
+  uint64_t total;
+  uint32_t seed;
+  uint32_t* y_out;                 // per sample Y
+  uint64_t* e_out;                 // per sample E (optional)
+  unsigned long long* seg_sums;    // 2 per segment: sum Y, sum E
+  unsigned long long* counter;     // work counter for the small-cascade kernel
+  unsigned long long* deferred;    // flat indices handed to the large-cascade kernel
+  unsigned int* ndeferred;
+  unsigned int* err;               // nonzero on an internal inconsistency
+  unsigned long long* large_sums;  // sum Y, sum E of the samples the large kernel finished
+  uint32_t chunk;                  // samples grabbed per counter increment
+  // large-cascade kernel workspace: per block a visited bitmap and a queue
+  uint32_t* bits;
+  int32_t* queue;
+  int64_t bits_words;
+  // backward accumulators (null in the forward)
+  const uint32_t* y_in;            // per-sample Y from the forward
+  unsigned long long* acc_live;    // per edge: sum of Y over samples where the edge is revealed live
+  unsigned long long* acc_dead;    // per edge: ... revealed dead
+  unsigned long long* acc_tab;     // per Stage-1 entry: sum of Y over samples with x_j = 1
+};
+
+// Hash used for the per-query seed set table (built on the host, probed on the device).
+__host__ __device__ inline uint32_t mix32(uint32_t v) {
+  v ^= v >> 16;
+  v *= 0x7feb352du;
+  v ^= v >> 15;
+  v *= 0x846ca68bu;
+  v ^= v >> 16;
+  return v;
+}
+
+constexpr int KIND_EDGE = 0;
+constexpr int KIND_SELECT = 1;
+constexpr int KIND_STAGE1 = 2;
+
+}  // namespace oi

@@ -1,0 +1,111 @@
+"""GPU parity of the stopping-rule controller (GSRA, Alg. 2; RSA, Alg. 3) and
+of SOIEA / SIEA (Algs. 4, 5): every RSA quantity (T1, h1, N_sigma, D, T, hT)
+and the returned fp64 estimates must equal the oracle's, and batched
+estimation must equal one-at-a-time estimation per seed set."""
+import numpy as np
+import pytest
+
+import oracle as O
+from oi_inputs import (chung_lu_graph, make_config, seed_node_outdeg_ge1, tiny16_graph, trivalency_probs,
+                       uniform_seed_set, wc_probs)
+from oi_inputs.configs import RUN_SEED
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("T1", "h1", "nsigma", "D", "T", "hT", "gsra_only", "early")
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_1704_04794_amd as P
+    return P
+
+
+def _check(P, G, g, S, eps, delta, mode, qid, label):
+    print(f"[gpu] rsa {label} |S|={len(S)} eps={eps} delta={delta} mode={mode} qid={qid}", flush=True)
+    a = G.estimate(S, eps, delta, mode=mode, query_id=qid)
+    b = O.estimate(g, S, eps, delta, mode, qid, RUN_SEED)
+    for f in FIELDS:
+        assert a[f] == b["rsa"][f], (label, f, a[f], b["rsa"][f])
+    assert a["mu"] == b["rsa"]["mu"] and a["mu1"] == b["rsa"]["mu1"]
+    assert a["oi"] == b["oi"] and a["is_"] == b["is_"] and a["beta0"] == b["beta0"]
+    assert a["k"] == b["k"]
+    return a
+
+
+def test_rsa_er2k(P):
+    g, sets, _ = make_config("er2k")
+    G = P.Graph.from_inputs(g)
+    for eps, delta, mode in [(0.1, 0.01, 0), (0.1, 0.01, 1), (0.3, 0.05, 0), (0.3, 0.05, 1), (0.05, 1e-3, 0),
+                             (0.2, 0.1, 1)]:
+        _check(P, G, g, sets[0], eps, delta, mode, 0, "er2k")
+    G.close()
+
+
+def test_rsa_tiny16_all_modes(P):
+    g = tiny16_graph()
+    G = P.Graph.from_inputs(g)
+    for S in ([0], [3, 7], [2, 5, 9], [12], [int(np.flatnonzero(g.outdeg() == 0)[0])]):
+        for mode in (0, 1):
+            a = _check(P, G, g, S, 0.1, 0.05, mode, 3, "tiny16")
+            assert a["is_"] == a["oi"] + a["k"] if mode == 0 else a["oi"] == a["is_"] - a["k"]
+    G.close()
+
+
+def test_rsa_small_rounds_same_answer(P):
+    """Many small rounds (crossings inside rounds, step 3 within drawn
+    samples, X' split over rounds) give the same result."""
+    g, sets, _ = make_config("er2k")
+    G = P.Graph.from_inputs(g)
+    G.tune(round_max=8192)
+    for eps, delta, mode in [(0.1, 0.01, 0), (0.05, 1e-3, 1)]:
+        _check(P, G, g, sets[0], eps, delta, mode, 0, "er2k rounds=8192")
+    G.close()
+
+
+def test_rsa_chung_lu(P):
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gt = g.with_p(trivalency_probs(g, 5))
+    G = P.Graph.from_inputs(gt)
+    S = seed_node_outdeg_ge1(gt, 3)
+    _check(P, G, gt, S, 0.2, 1e-3, 0, 0, "cl20k tri")
+    _check(P, G, gt, uniform_seed_set(gt, 30, 4), 0.2, 1e-3, 1, 1, "cl20k tri |S|=30")
+    G.close()
+    gw = g.with_p(wc_probs(g))
+    G = P.Graph.from_inputs(gw)
+    _check(P, G, gw, S, 0.2, 1e-2, 0, 2, "cl20k wc")
+    G.close()
+
+
+def test_batched_equals_single(P):
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gw = g.with_p(wc_probs(g))
+    G = P.Graph.from_inputs(gw)
+    rng = np.random.default_rng(8)
+    sets = [uniform_seed_set(gw, int(k), int(s)) for k, s in zip(rng.integers(1, 40, 12), rng.integers(0, 1 << 30, 12))]
+    sets.append(np.array([int(np.flatnonzero(gw.outdeg() == 0)[0])], np.int32))  # beta_0 = 0
+    qids = np.arange(100, 100 + len(sets), dtype=np.uint32)
+    for mode in (0, 1):
+        batch = G.estimate_batch(sets, 0.2, 1e-2, mode=mode, query_ids=qids)
+        for q, S in enumerate(sets):
+            one = G.estimate(S, 0.2, 1e-2, mode=mode, query_id=int(qids[q]))
+            for f in FIELDS + ("oi", "is_", "mu", "samples_x", "samples_xp"):
+                assert batch[q][f] == one[f], (q, f)
+        # and the oracle agrees on a few of them
+        for q in (0, 5, len(sets) - 1):
+            b = O.estimate(gw, sets[q], 0.2, 1e-2, mode, int(qids[q]), RUN_SEED)
+            assert batch[q]["oi"] == b["oi"] and batch[q]["T"] == b["rsa"]["T"]
+    G.close()
+
+
+def test_rsa_rejects_bad_parameters(P):
+    g = tiny16_graph()
+    G = P.Graph.from_inputs(g)
+    for eps, delta in [(0.0, 0.1), (1.0, 0.1), (0.1, 0.5), (0.1, 0.0), (float("nan"), 0.1)]:
+        with pytest.raises(P.OiError):
+            G.estimate([0], eps, delta)
+    with pytest.raises(P.OiError):
+        G.estimate([0], 0.1, 0.1, mode=2)
+    G.close()

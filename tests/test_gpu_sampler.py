@@ -1,0 +1,178 @@
+"""GPU parity of the IICP sampler (Alg. 1) and its Stage-1 table against the
+CPU oracle, through the C ABI.  Per-sample Y and examined-edge counts E are
+integers and must match bit for bit; Stage-1 tables must match exactly.
+
+Inputs come from oi_inputs (seeded); expected values only from oracle/.
+"""
+import numpy as np
+import pytest
+
+import oracle as O
+from oi_inputs import (chung_lu_graph, er_graph, fig1_graph, graph_from_edges, make_config, path_graph,
+                       seed_node_outdeg_ge1, star_graph, tiny16_graph, top_outdeg_seed_set, trivalency_probs,
+                       uniform_seed_set, wc_probs)
+from oi_inputs.configs import RUN_SEED
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible MI355X"
+    import paper_1704_04794_amd as P
+    return P
+
+
+def _gpu_graph(P, g):
+    return P.Graph.from_inputs(g)
+
+
+def _compare(P, g, S, N, first=0, stream=0, qid=0, G=None, variant=None, label=""):
+    print(f"[gpu] {label} n={g.n} m={g.m} |S|={len(np.atleast_1d(S))} N={N} first={first} stream={stream} "
+          f"variant={variant}", flush=True)
+    own = G is None
+    G = G or _gpu_graph(P, g)
+    if variant is not None:
+        G.tune(variant=variant)
+    y, e, r = G.sample_fixed(S, N, first=first, stream=stream, query_id=qid, want_e=True)
+    o = O.sample_fixed(g, S, qid, RUN_SEED, stream, first, N, want_e=True)
+    if o["beta0"] == 0.0:
+        assert r["beta0"] == 0.0 and r["sum_y"] == 0
+        return r
+    yg = y.cpu().numpy().view(np.uint32)
+    eg = e.cpu().numpy().view(np.uint64)
+    bad = np.flatnonzero(yg != o["y"])
+    assert bad.size == 0, (label, bad[:10], yg[bad[:10]], o["y"][bad[:10]])
+    np.testing.assert_array_equal(eg, o["e"])
+    assert r["sum_y"] == o["sum_y"] and r["edges_examined"] == o["sum_e"]
+    assert r["beta0"] == o["beta0"]
+    if own:
+        G.close()
+    return r
+
+
+def test_stage1_tables_bit_exact(P):
+    cases = [(fig1_graph(), [[0], [1], [2], [0, 1]]),
+             (tiny16_graph(), [[i] for i in range(16)] + [[0, 1, 2], [3, 7, 11], [5, 5, 9]])]
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    g = g.with_p(trivalency_probs(g, 5))
+    cases.append((g, [seed_node_outdeg_ge1(g, 3), uniform_seed_set(g, 50, 4), top_outdeg_seed_set(g, 300, 5)]))
+    h = graph_from_edges(5, [0, 0, 0, 1, 1, 1], [1, 2, 3, 0, 2, 4], [0.9, 0.5, 1.0, 0.7, 0.25, 0.0])
+    cases.append((h, [[0, 1], [1], [3]]))
+    for g, sets in cases:
+        G = _gpu_graph(P, g)
+        for S in sets:
+            a = G.stage1(S)
+            b = O.stage1(g, S)
+            assert a["l"] == b["l"] and a["beta0"] == b["beta0"]
+            np.testing.assert_array_equal(a["v"], b["v"])
+            np.testing.assert_array_equal(a["P"], b["P"])
+            np.testing.assert_array_equal(a["cdf"], b["cdf"])
+            np.testing.assert_array_equal(a["thr"], b["thr"])
+        G.close()
+
+
+def test_small_graphs_bit_exact(P):
+    g = fig1_graph(0.3)
+    for S in ([0], [1], [2], [0, 1]):
+        _compare(P, g, S, 20000, label="fig1")
+    _compare(P, star_graph(np.array([0.1, 0.3, 0.5, 0.8, 1.0, 0.0], np.float32)), [0], 20000, label="star")
+    _compare(P, path_graph(np.array([0.9, 0.8, 0.7, 0.6, 1.0], np.float32)), [0], 20000, label="path")
+    g = tiny16_graph()
+    G = _gpu_graph(P, g)
+    for v in range(16):
+        _compare(P, g, [v], 20000, qid=v, G=G, label=f"tiny16 {v}")
+    for S in ([0, 1, 2], [3, 7, 11], [2, 5, 9, 12]):
+        _compare(P, g, S, 20000, qid=7, G=G, label="tiny16 multi")
+    G.close()
+
+
+def test_er2k_workload_bit_exact(P):
+    """The ER n=2000 m=20000 weighted-cascade workload: 100,000 samples, query 0."""
+    g, sets, extra = make_config("er2k")
+    r = _compare(P, g, sets[0], extra["samples"], label="er2k")
+    assert r["beta0"] * r["sum_y"] / extra["samples"] > 0.0
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
+def test_variants_bit_exact(P, variant):
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gw = g.with_p(wc_probs(g))
+    G = _gpu_graph(P, gw)
+    G.timing(True)
+    S1 = seed_node_outdeg_ge1(gw, 3)
+    _compare(P, gw, S1, 30000, G=G, variant=variant, label="cl20k wc |S|=1")
+    _compare(P, gw, uniform_seed_set(gw, 20, 9), 20000, qid=3, G=G, variant=variant, label="cl20k wc |S|=20")
+    t = G.timing()
+    assert t["deferred"] > 0  # the large-cascade kernel took part
+    G.close()
+    gt = g.with_p(trivalency_probs(g, 5))
+    _compare(P, gt, S1, 50000, stream=1, first=123_457, variant=variant, label="cl20k tri X'")
+
+
+def test_large_seed_sets_and_hubs(P):
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gt = g.with_p(trivalency_probs(g, 5))
+    G = _gpu_graph(P, gt)
+    _compare(P, gt, top_outdeg_seed_set(gt, 500, 5), 5000, qid=11, G=G, label="tri top-500")
+    _compare(P, gt, uniform_seed_set(gt, 1000, 6), 5000, qid=12, G=G, label="tri uniform-1000")
+    G.close()
+    gw = g.with_p(wc_probs(g))
+    _compare(P, gw, top_outdeg_seed_set(gw, 200, 8), 3000, qid=13, label="wc top-200")
+    # a hub with 6000 out-edges reached in Stage 1: rows split over many passes
+    k = 6000
+    src = np.concatenate([[1], np.zeros(k, np.int64), np.arange(2, 40)])
+    dst = np.concatenate([[0], np.arange(2, k + 2), np.arange(3, 41)])
+    for p_hub in (0.01, 0.3):
+        p = np.concatenate([[0.9], np.full(k, p_hub), np.full(38, 0.5)]).astype(np.float32)
+        h = graph_from_edges(k + 2, src, dst, p)
+        _compare(P, h, [1], 4000, label=f"hub p={p_hub}")
+
+
+def test_cl1m_workload_sampled(P):
+    """The 1M-node Chung-Lu trivalency workload at full size: a 2^22-sample
+    launch on the GPU; 3,000 sample ids recomputed one by one by the oracle;
+    every sample checked against 1 <= Y <= n - |S| (Lemma 2)."""
+    g, sets, extra = make_config("cl1m")
+    S = sets[0]
+    G = _gpu_graph(P, g)
+    N = 1 << 22
+    print(f"[gpu] cl1m sampled N={N}", flush=True)
+    y, e, r = G.sample_fixed(S, N, want_e=True)
+    yg = y.cpu().numpy().view(np.uint32)
+    eg = e.cpu().numpy().view(np.uint64)
+    assert yg.min() >= 1 and yg.max() <= g.n - 1
+    assert int(yg.sum(dtype=np.uint64)) == r["sum_y"] and int(eg.sum(dtype=np.uint64)) == r["edges_examined"]
+    rng = np.random.default_rng(2)
+    ids = np.sort(rng.choice(N, size=3000, replace=False))
+    for i in ids:
+        o = O.sample_fixed(g, S, 0, RUN_SEED, 0, int(i), 1, want_e=True, nthreads=1)
+        assert yg[i] == o["y"][0] and eg[i] == o["e"][0], int(i)
+    # and one contiguous block in full
+    o = O.sample_fixed(g, S, 0, RUN_SEED, 0, 1_000_000, 50_000, want_e=True)
+    np.testing.assert_array_equal(yg[1_000_000:1_050_000], o["y"])
+    G.close()
+
+
+def test_degenerate_inputs(P):
+    g = tiny16_graph()
+    G = _gpu_graph(P, g)
+    leaf = int(np.flatnonzero(g.outdeg() == 0)[0])
+    y, e, r = G.sample_fixed([leaf], 100)
+    assert r["beta0"] == 0.0 and r["sum_y"] == 0
+    y, e, r = G.sample_fixed([0], 0)
+    assert r["sum_y"] == 0
+    with pytest.raises(P.OiError):
+        G.sample_fixed([16], 10)
+    with pytest.raises(P.OiError):
+        G.sample_fixed([], 10)
+    # all nodes in S: nothing outside S to activate
+    y, e, r = G.sample_fixed(list(range(16)), 10)
+    assert r["beta0"] == 0.0
+    G.close()
+    # an empty graph and a graph without edges out of S
+    h = graph_from_edges(3, [], [], [])
+    H = _gpu_graph(P, h)
+    assert H.sample_fixed([0], 10)[2]["beta0"] == 0.0
+    H.close()
