@@ -155,27 +155,33 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
                       uint64_t count, uint32_t run_seed, const uint32_t* y_in, oi_param param, double grad_scale,
                       float* grad_out);
 
-/* Kernel timing collected with HIP events on the graph's stream. */
+/* Kernel timing collected with HIP events on the graph's stream.  Every
+ * sampling launch runs three kernels: tiny (one sample per lane), small
+ * (several samples per wavefront) and large (one block per sample); a sample
+ * that outgrows one kernel is restarted from its key by the next. */
 typedef struct {
-  double small_ms;      /* total time of the small-cascade sampling kernel */
-  double large_ms;      /* total time of the large-cascade sampling kernel */
-  double other_ms;      /* reductions and backward finishing kernels */
-  uint64_t small_launches, large_launches;
-  uint64_t samples;     /* samples produced by sampling launches */
-  uint64_t deferred;    /* samples handed from the small to the large kernel */
-  uint64_t sum_y;       /* activated nodes (sum of Y) */
-  uint64_t edges;       /* examined edges (as in oi_result.edges_examined) */
-  uint64_t large_sum_y; /* the part of sum_y produced by the large-cascade kernel */
-  uint64_t large_edges; /* the part of edges examined by the large-cascade kernel */
+  double tiny_ms, small_ms, large_ms; /* summed kernel times */
+  uint64_t launches;                  /* sampling launches */
+  uint64_t samples;                   /* samples produced */
+  uint64_t handed_small;              /* samples passed from tiny to small */
+  uint64_t handed_large;              /* samples passed from small to large */
+  uint64_t tiny_y, tiny_edges;        /* sum of Y and examined edges of the samples each kernel finished */
+  uint64_t small_y, small_edges;
+  uint64_t large_y, large_edges;
 } oi_timing;
 
 /* enable != 0 turns event timing on (and resets the counters). */
 oi_status oi_timing_enable(oi_graph* g, int enable);
 oi_status oi_timing_get(oi_graph* g, oi_timing* out);
 
-/* Tuning of the small-cascade kernel: variant index (see oi_variant_info) and
- * samples taken per work-counter increment.  Values <= 0 keep the current one. */
-oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int64_t round_max);
+/* Tuning.  variant: small-kernel variant (see oi_variant_info); chunk:
+ * samples the small kernel takes per work-counter increment; tiny: 1 to run
+ * the one-sample-per-lane kernel first (default), 0 to start every sample in
+ * the small kernel; tiny_chunk: samples the tiny kernel takes per increment;
+ * round_max: samples per sampling launch (multiple of 4096).  Negative (or
+ * zero) values keep the current setting.  Results do not depend on any of
+ * these. */
+oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_chunk, int64_t round_max);
 int oi_num_variants(void);
 oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* ring_cap, int* rounds_per_pass);
 

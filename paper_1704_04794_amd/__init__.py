@@ -92,5 +92,5 @@ class Graph:
             oi_timing_enable(self.h, enable)
         return oi_timing_get(self.h)
 
-    def tune(self, variant=-1, chunk=-1, round_max=-1):
-        oi_set_tuning(self.h, variant, chunk, round_max)
+    def tune(self, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1):
+        oi_set_tuning(self.h, variant, chunk, tiny, tiny_chunk, round_max)

@@ -40,10 +40,11 @@ class oi_result(C.Structure):
 
 class oi_timing(C.Structure):
     _fields_ = [
-        ("small_ms", C.c_double), ("large_ms", C.c_double), ("other_ms", C.c_double),
-        ("small_launches", C.c_uint64), ("large_launches", C.c_uint64), ("samples", C.c_uint64),
-        ("deferred", C.c_uint64), ("sum_y", C.c_uint64), ("edges", C.c_uint64),
-        ("large_sum_y", C.c_uint64), ("large_edges", C.c_uint64),
+        ("tiny_ms", C.c_double), ("small_ms", C.c_double), ("large_ms", C.c_double),
+        ("launches", C.c_uint64), ("samples", C.c_uint64), ("handed_small", C.c_uint64),
+        ("handed_large", C.c_uint64), ("tiny_y", C.c_uint64), ("tiny_edges", C.c_uint64),
+        ("small_y", C.c_uint64), ("small_edges", C.c_uint64), ("large_y", C.c_uint64),
+        ("large_edges", C.c_uint64),
     ]
 
     def as_dict(self):
@@ -73,7 +74,7 @@ def _load():
         "oi_backward": [vp, u32, vp, i64, u64, u64, u32, vp, ci, dbl, vp],
         "oi_timing_enable": [vp, ci],
         "oi_timing_get": [vp, P(oi_timing)],
-        "oi_set_tuning": [vp, ci, ci, i64],
+        "oi_set_tuning": [vp, ci, ci, ci, ci, i64],
         "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
     }
     for name, args in sig.items():
@@ -215,8 +216,9 @@ def oi_timing_get(g):
     return t.as_dict()
 
 
-def oi_set_tuning(g, variant=-1, chunk=-1, round_max=-1):
-    _check("oi_set_tuning", _lib.oi_set_tuning(g, int(variant), int(chunk), int(round_max)))
+def oi_set_tuning(g, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1):
+    _check("oi_set_tuning", _lib.oi_set_tuning(g, int(variant), int(chunk), int(tiny), int(tiny_chunk),
+                                                int(round_max)))
 
 
 def oi_num_variants():

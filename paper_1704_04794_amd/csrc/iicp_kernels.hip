@@ -2,6 +2,11 @@
 // integer reductions the stopping rules need (Algs. 2 and 3).
 //
 // Sampling is split over two kernels:
+//   * tiny_kernel: persistent; every lane runs one sample as a small state
+//     machine (start / Stage-1 group / edge group / pop), with its visited
+//     list in LDS; each loop iteration costs one Philox block per lane.  A
+//     sample that would visit more than TINY_CAP nodes (or whose Stage-1
+//     table is long) is handed to small_kernel.
 //   * small_kernel: persistent; every wavefront runs K samples at once, each
 //     with a visited set in LDS (open addressing) and a shared LDS ring of
 //     pending expansion items.  Each pass the wave gathers up to 64 items,
@@ -135,6 +140,291 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
 }
 
 // ---------------------------------------------------------------------------
+// tiny_kernel: one sample per lane
+// ---------------------------------------------------------------------------
+constexpr uint32_t TINY_LMAX = 64;  // longest Stage-1 table the tiny kernel takes
+enum : uint32_t { T_IDLE = 0, T_START = 1, T_STAGE1 = 2, T_EXPAND = 3, T_POP = 4 };
+
+// Append the flat indices of the lanes with `pred` to a hand-over list.
+// Must be reached by the whole wave.
+__device__ __forceinline__ void hand_over(bool pred, uint64_t f, unsigned long long* list, unsigned int* nlist,
+                                          int lane) {
+  const unsigned long long m = __ballot(pred);
+  if (m) {
+    unsigned int base = 0;
+    if (lane == 0) base = atomicAdd(nlist, (unsigned int)__popcll(m));
+    base = (unsigned int)__builtin_amdgcn_readfirstlane((int)__shfl(base, 0, 64));
+    if (pred) list[base + lane_prefix(m)] = f;
+  }
+}
+
+template <int CAP, bool BWD>
+__global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
+  __shared__ int32_t vis_all[4][CAP * 64];
+  const int lane = threadIdx.x & 63;
+  int32_t* vis = &vis_all[threadIdx.x >> 6][lane];  // entry c of this lane at vis[64 * c]
+
+  // lane state; the query's fields are copied into registers when a sample
+  // starts, so no iteration re-reads shared structures
+  uint32_t st = T_IDLE;
+  uint64_t f = 0, s = 0, oidx = 0;
+  uint32_t sg = 0, stream = 0, cnt = 0, qh = 0, y = 0, g = 0, gend = 0;
+  uint32_t qid = 0, smask = 0;
+  int32_t qk = 0, s0 = 0;
+  int64_t ql = 0;
+  const TabGroup* tab = nullptr;
+  const int32_t* shash = nullptr;
+  unsigned long long E = 0;
+  int64_t lo_e = 0, hi_e = 0;
+  uint64_t cur = 0, cend = 0;
+  bool exhausted = false;
+  uint32_t acc_seg = 0xFFFFFFFFu;
+  unsigned long long acc_y = 0, acc_e = 0;
+
+  while (true) {
+    // (0) lanes whose queue is drained finish their sample
+    if (st == T_POP && qh == cnt) {
+      if (BWD) {
+        if (cnt != y) atomicOr(A.err, 2u);
+      } else {
+        A.y_out[oidx] = cnt;
+        if (A.e_out) A.e_out[oidx] = E;
+      }
+      if (sg != acc_seg) {
+        if (acc_seg != 0xFFFFFFFFu) {
+          atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
+          atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
+          atomicAdd(&A.tier_sums[0], acc_y);
+          atomicAdd(&A.tier_sums[1], acc_e);
+        }
+        acc_seg = sg;
+        acc_y = 0;
+        acc_e = 0;
+      }
+      acc_y += cnt;
+      acc_e += E;
+      st = T_IDLE;
+    }
+    // (1) idle lanes take the next samples of the wave's chunk
+    const unsigned long long idle = __ballot(st == T_IDLE);
+    if (idle && !exhausted) {
+      const uint32_t want = (uint32_t)__popcll(idle);
+      const uint32_t rank = lane_prefix(idle);
+      uint32_t given = 0;
+      while (given < want) {
+        if (cur >= cend) {
+          unsigned long long c = 0;
+          if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
+          c = uniform64(__shfl(c, 0, 64));
+          if (c >= A.total) {
+            exhausted = true;
+            break;
+          }
+          cur = c;
+          cend = c + A.tiny_chunk < A.total ? c + A.tiny_chunk : A.total;
+        }
+        const uint64_t room = cend - cur;
+        const uint32_t take = room < (uint64_t)(want - given) ? (uint32_t)room : want - given;
+        if (st == T_IDLE && rank >= given && rank < given + take) {
+          f = cur + (rank - given);
+          st = T_START;
+        }
+        cur += take;
+        given += take;
+      }
+    }
+    if (__ballot(st != T_IDLE) == 0ull) {
+      if (exhausted) break;
+      continue;
+    }
+    // (2) new samples: locate them and copy their query's fields.  Long
+    // Stage-1 tables (and, in the backward, samples known to be large) go
+    // straight to the small kernel.
+    bool pass_on = false;
+    if (st == T_START) {
+      sg = find_segment(A, f);
+      const Segment S = A.segs[sg];
+      stream = S.stream;
+      s = S.first + (f - S.flat0);
+      oidx = S.out_off + (f - S.flat0);
+      const QueryDev& Q = A.qs[S.q];
+      qid = Q.qid;
+      ql = Q.l;
+      qk = Q.k;
+      s0 = Q.s0;
+      smask = Q.smask;
+      shash = Q.shash;
+      tab = Q.tab;
+      pass_on = ql > (int64_t)TINY_LMAX;
+      if (BWD) {
+        y = A.y_in[oidx];
+        pass_on |= y > (uint32_t)CAP;
+      }
+      if (pass_on) st = T_IDLE;
+    }
+    hand_over(pass_on, f, A.list1, A.nlist1, lane);
+    pass_on = false;
+    // (3) one round of independent loads: popping lanes fetch the next
+    // node's row bounds, expanding lanes their group of four edges or table
+    // entries; then one Philox block per working lane
+    int32_t tv[4] = {0, 0, 0, 0};
+    float tp[4] = {0.f, 0.f, 0.f, 0.f};
+    uint64_t tt[4] = {0, 0, 0, 0};
+    int64_t peb = 0, pee = 0;
+    if (st == T_POP) {
+      const int32_t u = vis[64 * qh];
+      peb = A.row_ptr[u];
+      pee = A.row_ptr[u + 1];
+    } else if (st == T_EXPAND) {
+      const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
+      const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
+      tv[0] = vv.x; tv[1] = vv.y; tv[2] = vv.z; tv[3] = vv.w;
+      tp[0] = pp.x; tp[1] = pp.y; tp[2] = pp.z; tp[3] = pp.w;
+    } else if (st == T_STAGE1) {
+      const TabGroup T = tab[g];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        tv[b] = T.v[b];
+        tt[b] = T.thr[b];
+      }
+    }
+    Words d;
+    d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0;
+    if (st == T_START || st == T_STAGE1 || st == T_EXPAND) {
+      const uint32_t kind = st == T_START ? KIND_SELECT : (st == T_STAGE1 ? KIND_STAGE1 : KIND_EDGE);
+      d = philox_draw(qid, A.seed, kind, stream, s, st == T_START ? 0ull : (uint64_t)g);
+    }
+    // (4) consume
+    if (st == T_POP) {
+      ++qh;
+      E += (unsigned long long)(pee - peb);
+      if (pee > peb) {
+        lo_e = peb;
+        hi_e = pee;
+        g = (uint32_t)(peb >> 2);
+        gend = (uint32_t)((pee + 3) >> 2);
+        st = T_EXPAND;
+      }
+    } else if (st == T_START) {
+      // Stage 1, lines 2-3 of Alg. 1
+      const QueryDev& Q = A.qs[A.segs[sg].q];
+      int64_t i = 0;
+      if (ql > 1) {
+        const uint64_t a = d.w[0] >> 5, b = d.w[1] >> 6;
+        const double U = (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
+        const double t = U * Q.beta0;
+        int64_t lo = 0, hi = ql;
+        while (lo < hi) {
+          const int64_t mid = lo + ((hi - lo) >> 1);
+          if (Q.cdf[mid + 1] > t)
+            hi = mid;
+          else
+            lo = mid + 1;
+        }
+        i = lo;
+        if (lo >= ql) {
+          i = -1;
+          for (int64_t j = ql - 1; j >= 0; --j)
+            if (Q.cdf[j + 1] > Q.cdf[j]) {
+              i = j;
+              break;
+            }
+          if (i < 0) {
+            atomicOr(A.err, 1u);
+            i = 0;
+          }
+        }
+      }
+      const int32_t vi = tab[i >> 2].v[i & 3];
+      vis[0] = vi;
+      cnt = 1;
+      qh = 0;
+      E = (unsigned long long)(ql - 1 - i);
+      if (BWD) atomicAdd(&A.acc_tab[i], (unsigned long long)y);
+      if (i + 1 < ql) {
+        lo_e = i + 1;
+        hi_e = ql;
+        g = (uint32_t)((i + 1) >> 2);
+        gend = (uint32_t)((ql + 3) >> 2);
+        st = T_STAGE1;
+      } else {
+        st = T_POP;
+      }
+    } else if (st == T_STAGE1 || st == T_EXPAND) {
+      // Stage 1 lines 4-6 (table group) or Stage 2 lines 9-11 (edge group)
+      uint32_t live = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t x = 4 * (int64_t)g + b;
+        if (x >= lo_e && x < hi_e) {
+          if (st == T_STAGE1) {
+            if ((uint64_t)d.w[b] < tt[b]) {
+              live |= 1u << b;
+              if (BWD) atomicAdd(&A.acc_tab[x], (unsigned long long)y);
+            }
+          } else {
+            const bool lv = edge_live(d.w[b], tp[b]);
+            if (BWD || lv) {
+              bool ins = tv[b] == s0;
+              if (qk != 1) {
+                uint32_t h = mix32((uint32_t)tv[b]) & smask;
+                while (true) {
+                  const int32_t c = shash[h];
+                  if (c == tv[b]) {
+                    ins = true;
+                    break;
+                  }
+                  if (c < 0) {
+                    ins = false;
+                    break;
+                  }
+                  h = (h + 1) & smask;
+                }
+              }
+              if (!ins) {
+                if (BWD) atomicAdd(lv ? &A.acc_live[x] : &A.acc_dead[x], (unsigned long long)y);
+                if (lv) live |= 1u << b;
+              }
+            }
+          }
+        }
+      }
+      bool overflow = false;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        if ((live >> b) & 1u) {
+          const int32_t v = tv[b];
+          bool dup = false;
+          for (uint32_t c = 0; c < cnt; ++c) dup |= vis[64 * c] == v;
+          if (!dup) {
+            if (cnt >= (uint32_t)CAP) {
+              overflow = true;
+            } else {
+              vis[64 * cnt] = v;
+              ++cnt;
+            }
+          }
+        }
+      }
+      if (overflow) {
+        if (BWD) atomicOr(A.err, 8u);  // y_in said the sample fits
+        pass_on = !BWD;
+        st = T_IDLE;
+      } else if (++g >= gend) {
+        st = T_POP;
+      }
+    }
+    hand_over(pass_on, f, A.list1, A.nlist1, lane);
+  }
+  if (acc_seg != 0xFFFFFFFFu) {
+    atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
+    atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
+    atomicAdd(&A.tier_sums[0], acc_y);
+    atomicAdd(&A.tier_sums[1], acc_e);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // small_kernel
 // ---------------------------------------------------------------------------
 // Ring items (64 bits): a = node id (node item) or next Stage-1 entry index
@@ -233,6 +523,9 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
   bool exhausted = false;
   uint32_t acc_seg = 0xFFFFFFFFu;
   unsigned long long acc_y = 0, acc_e = 0;
+  const bool from_list = A.small_from_list1 != 0;
+  const uint64_t total = from_list ? (uint64_t)*A.nlist1 : A.total;
+  unsigned long long* const counter = from_list ? A.counter1 : A.counter;
 
   while (true) {
     // ---- refill free slots from the work counter ----------------------
@@ -242,17 +535,17 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
       if (uniform(W.s_active[k]) == 0u) {
         if (cur >= cend && !exhausted) {
           unsigned long long c = 0;
-          if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.chunk);
+          if (lane == 0) c = atomicAdd(counter, (unsigned long long)A.chunk);
           c = uniform64(__shfl(c, 0, 64));
-          if (c >= A.total) {
+          if (c >= total) {
             exhausted = true;
           } else {
             cur = c;
-            cend = c + A.chunk < A.total ? c + A.chunk : A.total;
+            cend = c + A.chunk < total ? c + A.chunk : total;
           }
         }
         if (cur < cend) {
-          if (lane == 0) W.s_f[k] = cur;
+          if (lane == 0) W.s_f[k] = from_list ? A.list1[cur] : cur;
           ++cur;
           newmask |= 1u << k;
         }
@@ -272,8 +565,8 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         if (BWD) {
           y = A.y_in[S.out_off + (f - S.flat0)];
           if (y > CMAX) {  // known too large for LDS: straight to the large kernel
-            const unsigned int pos = atomicAdd(A.ndeferred, 1u);
-            A.deferred[pos] = f;
+            const unsigned int pos = atomicAdd(A.nlist2, 1u);
+            A.list2[pos] = f;
             start = false;
           }
         }
@@ -489,8 +782,8 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
               if (BWD) {
                 atomicOr(A.err, 8u);
               } else {
-                const unsigned int pos = atomicAdd(A.ndeferred, 1u);
-                A.deferred[pos] = W.s_f[k];
+                const unsigned int pos = atomicAdd(A.nlist2, 1u);
+                A.list2[pos] = W.s_f[k];
               }
               W.s_active[k] = 0;
             }
@@ -559,6 +852,8 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
           if (lane == 0 && acc_seg != 0xFFFFFFFFu) {
             atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
             atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
+            atomicAdd(&A.tier_sums[2], acc_y);
+            atomicAdd(&A.tier_sums[3], acc_e);
           }
           acc_seg = sg;
           acc_y = 0;
@@ -573,6 +868,8 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
   if (lane == 0 && acc_seg != 0xFFFFFFFFu) {
     atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
     atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
+    atomicAdd(&A.tier_sums[2], acc_y);
+    atomicAdd(&A.tier_sums[3], acc_e);
   }
 }
 
@@ -611,9 +908,9 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
   const int tid = threadIdx.x;
   uint32_t* bits = A.bits + (int64_t)blockIdx.x * A.bits_words;
   int32_t* queue = A.queue + (int64_t)blockIdx.x * A.n;
-  const uint32_t nd = *A.ndeferred;
+  const uint32_t nd = *A.nlist2;
   for (uint32_t di = blockIdx.x; di < nd; di += gridDim.x) {
-    const uint64_t f = A.deferred[di];
+    const uint64_t f = A.list2[di];
     const uint32_t sg = find_segment(A, f);
     const Segment S = A.segs[sg];
     const QueryDev& Q = A.qs[S.q];
@@ -731,8 +1028,8 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       }
       atomicAdd(&A.seg_sums[2 * sg], (unsigned long long)Y);
       atomicAdd(&A.seg_sums[2 * sg + 1], s_E);
-      atomicAdd(&A.large_sums[0], (unsigned long long)Y);
-      atomicAdd(&A.large_sums[1], s_E);
+      atomicAdd(&A.tier_sums[4], (unsigned long long)Y);
+      atomicAdd(&A.tier_sums[5], s_E);
     }
     for (uint32_t t = tid; t < Y; t += LB) bits[queue[t] >> 5] = 0u;
     __syncthreads();
@@ -775,37 +1072,67 @@ __device__ __forceinline__ void add128(unsigned long long& lo, unsigned long lon
   lo = n;
 }
 
+__device__ __forceinline__ void flush128(unsigned long long* acc, unsigned long long lo, unsigned long long hi) {
+  const unsigned long long old = atomicAdd(&acc[0], lo);
+  atomicAdd(&acc[1], hi + (old + lo < old ? 1ull : 0ull));
+}
+
+// One pass per block over a contiguous range of pairs; partial sums are
+// reduced across the block before a single 128-bit atomic per segment run.
 __global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const PairSeg* ps, int32_t nps,
-                                                      uint64_t total, unsigned long long* acc) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int32_t cur = -1;
-  unsigned long long lo = 0, hi = 0;
-  for (; i < total; i += stride) {
+                                                      uint64_t total, uint64_t per_block, unsigned long long* acc) {
+  __shared__ unsigned long long red_lo[4], red_hi[4];
+  const uint64_t b0 = (uint64_t)blockIdx.x * per_block;
+  const uint64_t b1 = b0 + per_block < total ? b0 + per_block : total;
+  if (b0 >= b1) return;
+  // segment of the block's first pair; blocks are small next to segments,
+  // so a block crosses few segment boundaries
+  int32_t seg = 0;
+  {
     int32_t a = 0, b = nps - 1;
     while (a < b) {
       const int32_t mid = (a + b + 1) >> 1;
-      if (ps[mid].flat0 <= i)
+      if (ps[mid].flat0 <= b0)
         a = mid;
       else
         b = mid - 1;
     }
-    if (a != cur) {
-      if (cur >= 0 && (lo | hi)) {
-        const unsigned long long old = atomicAdd(&acc[2 * ps[cur].acc], lo);
-        atomicAdd(&acc[2 * ps[cur].acc + 1], hi + (old + lo < old ? 1ull : 0ull));
-      }
-      cur = a;
-      lo = hi = 0;
-    }
-    const uint64_t p = ps[a].out_off + 2 * (i - ps[a].flat0);
-    const uint32_t y0 = y[p], y1 = y[p + 1];
-    const unsigned long long d = y0 > y1 ? (unsigned long long)(y0 - y1) : (unsigned long long)(y1 - y0);
-    add128(lo, hi, d * d, 0);
+    seg = a;
   }
-  if (cur >= 0 && (lo | hi)) {
-    const unsigned long long old = atomicAdd(&acc[2 * ps[cur].acc], lo);
-    atomicAdd(&acc[2 * ps[cur].acc + 1], hi + (old + lo < old ? 1ull : 0ull));
+  uint64_t lo_pair = b0;
+  while (lo_pair < b1 && seg < nps) {
+    const PairSeg P = ps[seg];
+    const uint64_t seg_end = P.flat0 + P.npairs;
+    const uint64_t hi_pair = seg_end < b1 ? seg_end : b1;
+    if (hi_pair <= lo_pair) {  // empty segment
+      ++seg;
+      continue;
+    }
+    unsigned long long lo = 0, hi = 0;
+    for (uint64_t i = lo_pair + threadIdx.x; i < hi_pair; i += 256) {
+      const uint64_t p = P.out_off + 2 * (i - P.flat0);
+      const uint2 v = *reinterpret_cast<const uint2*>(&y[p]);
+      const unsigned long long d = v.x > v.y ? (unsigned long long)(v.x - v.y) : (unsigned long long)(v.y - v.x);
+      add128(lo, hi, d * d, 0);
+    }
+#pragma unroll
+    for (int sh = 32; sh > 0; sh >>= 1) {
+      const unsigned long long olo = __shfl_down(lo, sh, 64), ohi = __shfl_down(hi, sh, 64);
+      add128(lo, hi, olo, ohi);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red_lo[threadIdx.x >> 6] = lo;
+      red_hi[threadIdx.x >> 6] = hi;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      unsigned long long L = 0, H = 0;
+      for (int w = 0; w < 4; ++w) add128(L, H, red_lo[w], red_hi[w]);
+      if (L | H) flush128(&acc[2 * P.acc], L, H);
+    }
+    __syncthreads();
+    lo_pair = hi_pair;
+    ++seg;
   }
 }
 
@@ -914,6 +1241,26 @@ hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipS
   return hipLaunchKernel(bwd ? s.bwd : s.fwd, dim3(blocks), dim3(256), args, 0, st);
 }
 
+constexpr int TINY_CAP = 16;
+
+int tiny_cap() { return TINY_CAP; }
+
+hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu,
+      bwd ? reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true>)
+          : reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false>),
+      256, 0);
+}
+
+hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
+  if (bwd)
+    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, true>), dim3(blocks), dim3(256), 0, st, A);
+  else
+    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false>), dim3(blocks), dim3(256), 0, st, A);
+  return hipGetLastError();
+}
+
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
   if (bwd)
     hipLaunchKernelGGL(large_kernel<true>, dim3(blocks), dim3(LB), 0, st, A);
@@ -933,10 +1280,10 @@ hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, uns
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
                           hipStream_t st) {
   if (total == 0) return hipSuccess;
-  uint64_t blocks = (total + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  const uint64_t per_block = 8192;  // pairs per block: 64 KB of Y
+  const uint64_t blocks = (total + per_block - 1) / per_block;
   hipLaunchKernelGGL(pair_sq_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y,
-                     reinterpret_cast<const PairSeg*>(ps), nps, total, acc);
+                     reinterpret_cast<const PairSeg*>(ps), nps, total, per_block, acc);
   return hipGetLastError();
 }
 

@@ -25,6 +25,9 @@ void small_variant_info(int v, int* k, int* hcap, int* rcap, int* r);
 hipError_t small_occupancy(int v, bool bwd, int* blocks_per_cu);
 hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
+int tiny_cap();
+hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu);
+hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, unsigned long long* out, hipStream_t st);
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
                           hipStream_t st);
@@ -100,14 +103,16 @@ struct oi_graph {
   std::vector<float> p;
   DevBuf d_row_ptr, d_eg;
   // per-launch workspaces
-  DevBuf d_y, d_def, d_ctl, d_segs, d_qs, d_sums, d_chunks, d_pairs, d_pacc, d_bits, d_queue;
+  DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_chunks, d_pairs, d_pacc, d_bits, d_queue;
   int large_blocks = 0;
   int variant = 0;
+  bool use_tiny = true;
   uint32_t chunk = 256;
+  uint32_t tiny_chunk = 1024;
   uint64_t round_max = 1ull << 26;
   // timing
   bool timing = false;
-  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
   oi_timing tm{};
 };
 
@@ -277,12 +282,15 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   HIP_TRY(g->d_qs.ensure(qd.size() * sizeof(oi::QueryDev)));
   HIP_TRY(g->d_sums.ensure(sums.size() * sizeof(unsigned long long)));
   HIP_TRY(g->d_def.ensure(total * sizeof(unsigned long long)));
-  HIP_TRY(g->d_ctl.ensure(64));
+  HIP_TRY(g->d_def2.ensure(total * sizeof(unsigned long long)));
+  HIP_TRY(g->d_ctl.ensure(16 * sizeof(unsigned long long)));
   HIP_TRY(hipMemcpyAsync(g->d_segs.p, ds.data(), ds.size() * sizeof(oi::Segment), hipMemcpyHostToDevice, g->stream));
   HIP_TRY(hipMemcpyAsync(g->d_qs.p, qd.data(), qd.size() * sizeof(oi::QueryDev), hipMemcpyHostToDevice, g->stream));
   HIP_TRY(hipMemsetAsync(g->d_sums.p, 0, sums.size() * sizeof(unsigned long long), g->stream));
-  HIP_TRY(hipMemsetAsync(g->d_ctl.p, 0, 64, g->stream));
+  HIP_TRY(hipMemsetAsync(g->d_ctl.p, 0, 16 * sizeof(unsigned long long), g->stream));
 
+  // control block: [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier sums
+  unsigned long long* ctl = g->d_ctl.as<unsigned long long>();
   oi::SampleLaunch A{};
   A.n = g->n;
   A.row_ptr = g->d_row_ptr.as<int64_t>();
@@ -295,13 +303,17 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   A.y_out = y_dev;
   A.e_out = e_dev;
   A.seg_sums = g->d_sums.as<unsigned long long>();
-  unsigned long long* ctl = g->d_ctl.as<unsigned long long>();
+  A.tier_sums = ctl + 5;
   A.counter = ctl;
-  A.ndeferred = reinterpret_cast<unsigned int*>(ctl + 1);
-  A.err = reinterpret_cast<unsigned int*>(ctl + 2);
-  A.large_sums = ctl + 3;
-  A.deferred = g->d_def.as<unsigned long long>();
+  A.counter1 = ctl + 1;
+  A.list1 = g->d_def.as<unsigned long long>();
+  A.nlist1 = reinterpret_cast<unsigned int*>(ctl + 2);
+  A.list2 = g->d_def2.as<unsigned long long>();
+  A.nlist2 = reinterpret_cast<unsigned int*>(ctl + 3);
+  A.small_from_list1 = g->use_tiny ? 1 : 0;
+  A.err = reinterpret_cast<unsigned int*>(ctl + 4);
   A.chunk = g->chunk;
+  A.tiny_chunk = g->tiny_chunk;
   A.bits = g->d_bits.as<uint32_t>();
   A.queue = g->d_queue.as<int32_t>();
   A.bits_words = (g->n + 31) / 32;
@@ -312,41 +324,54 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     A.acc_dead = bwd->dead;
     A.acc_tab = bwd->tab;
   }
+  const uint64_t want_waves = (total + 63) / 64;
   int bpc = 0;
+  if (g->timing) HIP_TRY(hipEventRecord(g->ev[0], g->stream));
+  if (g->use_tiny) {
+    HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
+    if (bpc < 1) bpc = 1;
+    const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
+    HIP_TRY(oi::launch_tiny(is_bwd, A, blocks, g->stream));
+  }
+  if (g->timing) HIP_TRY(hipEventRecord(g->ev[1], g->stream));
   HIP_TRY(oi::small_occupancy(g->variant, is_bwd, &bpc));
   if (bpc < 1) bpc = 1;
-  uint64_t want = (total + 63) / 64;  // never more waves than needed
-  int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want + 3) / 4));
-  if (g->timing) HIP_TRY(hipEventRecord(g->ev[0], g->stream));
-  HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, g->stream));
-  if (g->timing) HIP_TRY(hipEventRecord(g->ev[1], g->stream));
-  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
+  {
+    // the small kernel sees only what the tiny kernel handed over; its grid
+    // must not depend on that count (it is on the device), so it is sized
+    // for the whole launch and idle waves exit at once
+    const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
+    HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, g->stream));
+  }
   if (g->timing) HIP_TRY(hipEventRecord(g->ev[2], g->stream));
-  unsigned long long hctl[5] = {0, 0, 0, 0, 0};
+  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
+  if (g->timing) HIP_TRY(hipEventRecord(g->ev[3], g->stream));
+  unsigned long long hctl[16] = {0};
   HIP_TRY(hipMemcpyAsync(sums.data(), g->d_sums.p, sums.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                          g->stream));
   HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
-  const unsigned int ndef = (unsigned int)(hctl[1] & 0xffffffffull);
-  const unsigned int err = (unsigned int)(hctl[2] & 0xffffffffull);
+  const unsigned int err = (unsigned int)(hctl[4] & 0xffffffffull);
   if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
   if (rounds) ++*rounds;
   if (g->timing) {
-    float a = 0, b = 0;
-    HIP_TRY(hipEventElapsedTime(&a, g->ev[0], g->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&b, g->ev[1], g->ev[2]));
-    g->tm.small_ms += a;
-    g->tm.large_ms += b;
-    g->tm.small_launches += 1;
-    g->tm.large_launches += 1;
+    float t0 = 0, t1 = 0, t2 = 0;
+    HIP_TRY(hipEventElapsedTime(&t0, g->ev[0], g->ev[1]));
+    HIP_TRY(hipEventElapsedTime(&t1, g->ev[1], g->ev[2]));
+    HIP_TRY(hipEventElapsedTime(&t2, g->ev[2], g->ev[3]));
+    g->tm.tiny_ms += t0;
+    g->tm.small_ms += t1;
+    g->tm.large_ms += t2;
+    g->tm.launches += 1;
     g->tm.samples += total;
-    g->tm.deferred += ndef;
-    for (size_t i = 0; i < segs.size(); ++i) {
-      g->tm.sum_y += sums[2 * i];
-      g->tm.edges += sums[2 * i + 1];
-    }
-    g->tm.large_sum_y += hctl[3];
-    g->tm.large_edges += hctl[4];
+    g->tm.handed_small += hctl[2] & 0xffffffffull;
+    g->tm.handed_large += hctl[3] & 0xffffffffull;
+    g->tm.tiny_y += hctl[5];
+    g->tm.tiny_edges += hctl[6];
+    g->tm.small_y += hctl[7];
+    g->tm.small_edges += hctl[8];
+    g->tm.large_y += hctl[9];
+    g->tm.large_edges += hctl[10];
   }
   return OI_OK;
 }
@@ -770,7 +795,7 @@ oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const in
   HIP_TRY(g->d_row_ptr.ensure(((size_t)n + 1) * 8));
   HIP_TRY(hipMemcpy(g->d_row_ptr.p, g->row_ptr.data(), ((size_t)n + 1) * 8, hipMemcpyHostToDevice));
   OI_TRY(upload_graph(g.get()));
-  for (int i = 0; i < 3; ++i) HIP_TRY(hipEventCreate(&g->ev[i]));
+  for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&g->ev[i]));
   *out = g.release();
   return OI_OK;
 }
@@ -798,7 +823,7 @@ oi_status oi_set_stream(oi_graph* g, void* hip_stream) {
 void oi_graph_destroy(oi_graph* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
-  for (int i = 0; i < 3; ++i)
+  for (int i = 0; i < 4; ++i)
     if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
   delete g;
 }
@@ -966,11 +991,13 @@ oi_status oi_timing_get(oi_graph* g, oi_timing* out) {
   return OI_OK;
 }
 
-oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int64_t round_max) {
+oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_chunk, int64_t round_max) {
   if (!g) return fail(OI_EINVAL, "null graph");
   if (variant >= oi::num_small_variants()) return fail(OI_EINVAL, "unknown variant");
   if (variant >= 0) g->variant = variant;
   if (chunk > 0) g->chunk = (uint32_t)chunk;
+  if (tiny >= 0) g->use_tiny = tiny != 0;
+  if (tiny_chunk > 0) g->tiny_chunk = (uint32_t)tiny_chunk;
   if (round_max > 0) {
     if (round_max % kChunk) return fail(OI_EINVAL, "round_max must be a multiple of 4096");
     if (round_max > (1ll << 31)) return fail(OI_ERANGE, "round_max above 2^31");

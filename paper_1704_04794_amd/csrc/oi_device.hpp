@@ -51,6 +51,11 @@ struct Segment {
   uint64_t flat0;
 };
 
+// One sampling launch.  Samples pass through up to three kernels, each of
+// which either finishes a sample or hands it (by flat index) to the next:
+//   tiny  (one sample per lane, <= TINY_CAP visited nodes)  -> list1
+//   small (several samples per wavefront, LDS visited sets) -> list2
+//   large (one block per sample, global bitmap)
 struct SampleLaunch {
   int64_t n;
   const int64_t* row_ptr;
@@ -63,12 +68,17 @@ struct SampleLaunch {
   uint32_t* y_out;                 // per sample Y
   uint64_t* e_out;                 // per sample E (optional)
   unsigned long long* seg_sums;    // 2 per segment: sum Y, sum E
-  unsigned long long* counter;     // work counter for the small-cascade kernel
-  unsigned long long* deferred;    // flat indices handed to the large-cascade kernel
-  unsigned int* ndeferred;
+  unsigned long long* tier_sums;   // 2 per kernel (tiny, small, large): sum Y, sum E it finished
+  unsigned long long* counter;     // flat work counter of the first kernel
+  unsigned long long* counter1;    // work counter of the small kernel over list1
+  unsigned long long* list1;       // flat indices handed from tiny to small
+  unsigned int* nlist1;
+  unsigned long long* list2;       // flat indices handed from small to large
+  unsigned int* nlist2;
+  int32_t small_from_list1;        // 1 if the tiny kernel ran before the small one
   unsigned int* err;               // nonzero on an internal inconsistency
-  unsigned long long* large_sums;  // sum Y, sum E of the samples the large kernel finished
-  uint32_t chunk;                  // samples grabbed per counter increment
+  uint32_t chunk;                  // samples the small kernel takes per counter increment
+  uint32_t tiny_chunk;             // samples the tiny kernel takes per counter increment
   // large-cascade kernel workspace: per block a visited bitmap and a queue
   uint32_t* bits;
   int32_t* queue;

@@ -95,20 +95,29 @@ def test_er2k_workload_bit_exact(P):
     assert r["beta0"] * r["sum_y"] / extra["samples"] > 0.0
 
 
-@pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 5])
-def test_variants_bit_exact(P, variant):
+@pytest.mark.parametrize("variant,tiny", [(0, 1), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (0, 0), (1, 0)])
+def test_variants_bit_exact(P, variant, tiny):
     g = chung_lu_graph(20000, 200000, 2.1, 7)
     gw = g.with_p(wc_probs(g))
     G = _gpu_graph(P, gw)
+    G.tune(tiny=tiny)
     G.timing(True)
     S1 = seed_node_outdeg_ge1(gw, 3)
-    _compare(P, gw, S1, 30000, G=G, variant=variant, label="cl20k wc |S|=1")
+    _compare(P, gw, S1, 30000, G=G, variant=variant, label=f"cl20k wc |S|=1 tiny={tiny}")
     _compare(P, gw, uniform_seed_set(gw, 20, 9), 20000, qid=3, G=G, variant=variant, label="cl20k wc |S|=20")
     t = G.timing()
-    assert t["deferred"] > 0  # the large-cascade kernel took part
+    # every kernel of the pipeline finished some of the samples
+    assert t["handed_large"] > 0 and t["large_y"] > 0 and t["small_y"] > 0
+    if tiny:
+        assert t["handed_small"] > 0 and t["tiny_y"] > 0
+    else:
+        assert t["tiny_y"] == 0
     G.close()
     gt = g.with_p(trivalency_probs(g, 5))
-    _compare(P, gt, S1, 50000, stream=1, first=123_457, variant=variant, label="cl20k tri X'")
+    G = _gpu_graph(P, gt)
+    G.tune(tiny=tiny)
+    _compare(P, gt, S1, 50000, stream=1, first=123_457, G=G, variant=variant, label="cl20k tri X'")
+    G.close()
 
 
 def test_large_seed_sets_and_hubs(P):
