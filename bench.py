@@ -55,6 +55,48 @@ def cpu_baseline(g, S, seconds):
                       f"{nt} threads), {dt:.1f} s; GTEPS {r['sum_e'] / dt / 1e9:.4f}"}
 
 
+def batched_vs_single(P, args):
+    """Seed-set estimates/s on the 4M-node weighted-cascade workload: a seeded
+    stratified subset of its 4,096 seed sets (equal numbers from the uniform
+    and the top-1% halves), estimated in one batched call and one at a time."""
+    import numpy as np
+
+    from oi_inputs import make_config
+    t = time.perf_counter()
+    g, sets, extra = make_config("cl4m")
+    log(f"cl4m graph n={g.n} m={g.m} built in {time.perf_counter() - t:.1f}s")
+    half = len(sets) // 2
+    k = max(1, args.queries // 2)
+    rng = np.random.default_rng(7)
+    pick = np.concatenate([rng.choice(half, size=k, replace=False),
+                           half + rng.choice(len(sets) - half, size=k, replace=False)])
+    sub = [sets[i] for i in pick]
+    qids = pick.astype(np.uint32)
+    eps = args.eps if args.eps > 0 else extra["eps"]
+    delta = extra["delta"]
+    G = P.Graph.from_inputs(g)
+    G.estimate(sub[0], 0.5, delta, query_id=int(qids[0]))  # warm up kernels and workspaces
+    import torch
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batch = G.estimate_batch(sub, eps, delta, query_ids=qids)
+    tb = time.perf_counter() - t
+    log(f"batched: {len(sub)} sets in {tb:.2f}s")
+    t = time.perf_counter()
+    single = [G.estimate(S, eps, delta, query_id=int(q)) for S, q in zip(sub, qids)]
+    ts = time.perf_counter() - t
+    log(f"one at a time: {len(sub)} sets in {ts:.2f}s")
+    same = all(a["oi"] == b["oi"] and a["T"] == b["T"] for a, b in zip(batch, single))
+    samples = sum(r["samples_x"] + r["samples_xp"] for r in batch)
+    G.close()
+    return {"metric": "seed-set estimates/s, batched vs one at a time", "workload":
+            f"cl4m: Chung-Lu n=4e6 m~7e7 gamma=2.1 WC p, {len(sub)} of the 4,096 seed sets "
+            f"({k} uniform + {k} top-1% out-degree, |S| in [1,1000]), SOIEA eps={eps} delta={delta}",
+            "batched_estimates_per_s": len(sub) / tb, "single_estimates_per_s": len(sub) / ts,
+            "speedup": ts / tb, "identical_results": same, "samples": samples,
+            "batched_samples_per_s": samples / tb}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +105,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--workload", choices=("cl1m", "cl4m"), default="cl1m",
+                    help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time")
+    ap.add_argument("--queries", type=int, default=32, help="cl4m: number of seed sets in the subset")
+    ap.add_argument("--eps", type=float, default=-1.0, help="cl4m: eps (default: the workload's 0.1)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first copy 1 GiB device-to-device with torch (a plain copy kernel of known size, "
+                         "to scale hardware byte counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
@@ -78,6 +127,16 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.workload == "cl4m":
+        print(json.dumps(batched_vs_single(P, args)), flush=True)
+        return
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copied 1 GiB device-to-device for counter calibration")
     t = time.perf_counter()
     g, sets, extra = make_config("cl1m")
     S = sets[0]

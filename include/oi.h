@@ -92,6 +92,14 @@ oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const in
 /* Replace all m edge probabilities (same topology).  p as in oi_graph_create. */
 oi_status oi_graph_set_probs(oi_graph* g, const float* p, int device_ptr);
 
+/* Set p_e = sigmoid(theta_e) for all m edges (evaluated in fp64 on the GPU,
+ * rounded to fp32); theta: float[m], device pointer if device_ptr != 0,
+ * else host.  Used with OI_PARAM_THETA gradients. */
+oi_status oi_graph_set_theta(oi_graph* g, const float* theta, int device_ptr);
+
+/* Copy the m edge probabilities the library currently uses to host p_out. */
+oi_status oi_graph_get_probs(oi_graph* g, float* p_out);
+
 /* Change the HIP stream used for the graph's work. */
 oi_status oi_set_stream(oi_graph* g, void* hip_stream);
 
@@ -177,7 +185,8 @@ oi_status oi_timing_get(oi_graph* g, oi_timing* out);
 /* Tuning.  variant: small-kernel variant (see oi_variant_info); chunk:
  * samples the small kernel takes per work-counter increment; tiny: 1 to run
  * the one-sample-per-lane kernel first (default), 0 to start every sample in
- * the small kernel; tiny_chunk: samples the tiny kernel takes per increment;
+ * the small kernel; tiny_chunk: samples the tiny kernel takes per increment
+ * (0 = automatic, the default; negative keeps the current setting);
  * round_max: samples per sampling launch (multiple of 4096).  Negative (or
  * zero) values keep the current setting.  Results do not depend on any of
  * these. */

@@ -10,7 +10,8 @@ import numpy as np
 
 from ._binding import (  # noqa: F401
     LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_backward,
-    oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_set_probs, oi_last_error,
+    oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
+    oi_graph_set_theta, oi_last_error,
     oi_num_variants, oi_sample_fixed, oi_set_stream, oi_set_tuning, oi_stage1_table, oi_timing_enable,
     oi_timing_get, oi_variant_info)
 
@@ -59,6 +60,15 @@ class Graph:
         dev = _is_device_tensor(p)
         oi_graph_set_probs(self.h, p.contiguous() if dev else np.ascontiguousarray(p, np.float32),
                            1 if dev else 0)
+
+    def set_theta(self, theta):
+        """p = sigmoid(theta), computed by the library on the GPU."""
+        dev = _is_device_tensor(theta)
+        oi_graph_set_theta(self.h, theta.contiguous() if dev else np.ascontiguousarray(theta, np.float32),
+                           1 if dev else 0)
+
+    def probs(self):
+        return oi_graph_get_probs(self.h, self.m)
 
     def stage1(self, seeds):
         return oi_stage1_table(self.h, seeds)

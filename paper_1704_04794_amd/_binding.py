@@ -67,6 +67,8 @@ def _load():
         "oi_graph_create": [i64, i64, vp, vp, vp, ci, vp, P(vp)],
         "oi_graph_set_probs": [vp, vp, ci],
         "oi_set_stream": [vp, vp],
+        "oi_graph_set_theta": [vp, vp, ci],
+        "oi_graph_get_probs": [vp, vp],
         "oi_stage1_table": [vp, vp, i64, i64, P(i64), P(dbl), vp, vp, vp, vp],
         "oi_sample_fixed": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
         "oi_estimate": [vp, u32, vp, i64, dbl, dbl, ci, u32, P(oi_result)],
@@ -144,6 +146,16 @@ def oi_graph_create(n, m, row_ptr, col, p, device_ptrs=0, hip_stream=None):
 
 def oi_graph_set_probs(g, p, device_ptr=0):
     _check("oi_graph_set_probs", _lib.oi_graph_set_probs(g, _ptr(p), int(device_ptr)))
+
+
+def oi_graph_set_theta(g, theta, device_ptr=0):
+    _check("oi_graph_set_theta", _lib.oi_graph_set_theta(g, _ptr(theta), int(device_ptr)))
+
+
+def oi_graph_get_probs(g, m):
+    out = np.zeros(int(m), np.float32)
+    _check("oi_graph_get_probs", _lib.oi_graph_get_probs(g, _ptr(out)))
+    return out
 
 
 def oi_set_stream(g, hip_stream):

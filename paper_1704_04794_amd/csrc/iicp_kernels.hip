@@ -60,6 +60,47 @@ __device__ __forceinline__ Words philox_draw(uint32_t k0, uint32_t k1, uint32_t 
   return o;
 }
 
+// Pointers read out of device structures are generic; these casts let the
+// compiler issue global (not flat) loads through them.
+#define OI_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const OI_GLOBAL T* gptr(const T* p) {
+  return (const OI_GLOBAL T*)p;
+}
+// Launch-invariant data (segments, query descriptors) read through the
+// constant address space: wave-uniform loads from it become scalar loads.
+#define OI_CONST __attribute__((address_space(4)))
+template <typename T>
+__device__ __forceinline__ const OI_CONST T* cptr(const T* p) {
+  return (const OI_CONST T*)p;
+}
+
+typedef int v4i32 __attribute__((ext_vector_type(4)));
+typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ TabGroup load_tab(const TabGroup* base, int64_t g) {
+  const OI_GLOBAL char* p = (const OI_GLOBAL char*)(gptr(base) + g);
+  const v4i32 v = *(const OI_GLOBAL v4i32*)p;
+  const v2u64 t0 = *(const OI_GLOBAL v2u64*)(p + 16);
+  const v2u64 t1 = *(const OI_GLOBAL v2u64*)(p + 32);
+  TabGroup T;
+  T.v[0] = v.x;
+  T.v[1] = v.y;
+  T.v[2] = v.z;
+  T.v[3] = v.w;
+  T.thr[0] = t0.x;
+  T.thr[1] = t0.y;
+  T.thr[2] = t1.x;
+  T.thr[3] = t1.y;
+  return T;
+}
+
+// v of Stage-1 entry j
+__device__ __forceinline__ int32_t tab_v(const TabGroup* base, int64_t j) {
+  const OI_GLOBAL char* p = (const OI_GLOBAL char*)(gptr(base) + (j >> 2));
+  return *(const OI_GLOBAL int32_t*)(p + 4 * (j & 3));
+}
+
 // Live iff word < floor(p * 2^32).  p * 2^32 is exact in fp32 for p in [0, 1)
 // and the conversion truncates, which is the floor; p = 1 is always live.
 __device__ __forceinline__ bool edge_live(uint32_t word, float p) {
@@ -73,17 +114,18 @@ __device__ int64_t select_entry(const QueryDev& Q, uint32_t seed, uint32_t strea
   const uint64_t a = d.w[0] >> 5, b = d.w[1] >> 6;
   const double U = (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
   const double t = U * Q.beta0;
+  const OI_GLOBAL double* cdf = gptr(Q.cdf);
   int64_t lo = 0, hi = Q.l;
   while (lo < hi) {
     const int64_t mid = lo + ((hi - lo) >> 1);
-    if (Q.cdf[mid + 1] > t)
+    if (cdf[mid + 1] > t)
       hi = mid;
     else
       lo = mid + 1;
   }
   if (lo < Q.l) return lo;
   for (int64_t j = Q.l - 1; j >= 0; --j)
-    if (Q.cdf[j + 1] > Q.cdf[j]) return j;
+    if (cdf[j + 1] > cdf[j]) return j;
   return -1;
 }
 
@@ -91,11 +133,37 @@ __device__ __forceinline__ bool in_seed_set(const QueryDev& Q, int32_t v) {
   if (Q.k == 1) return v == Q.s0;
   uint32_t h = mix32((uint32_t)v) & Q.smask;
   while (true) {
-    const int32_t c = Q.shash[h];
+    const int32_t c = gptr(Q.shash)[h];
     if (c == v) return true;
     if (c < 0) return false;
     h = (h + 1) & Q.smask;
   }
+}
+
+__device__ __forceinline__ bool in_seed_fields(int32_t k, int32_t s0, uint32_t smask, const int32_t* shash,
+                                               int32_t v) {
+  if (k == 1) return v == s0;
+  uint32_t h = mix32((uint32_t)v) & smask;
+  while (true) {
+    const int32_t c = gptr(shash)[h];
+    if (c == v) return true;
+    if (c < 0) return false;
+    h = (h + 1) & smask;
+  }
+}
+
+// find_segment for a wave-uniform flat index (scalar loads)
+__device__ __forceinline__ uint32_t find_segment_uniform(const SampleLaunch& A, uint64_t f) {
+  const OI_CONST Segment* segs = cptr(A.segs);
+  int32_t lo = 0, hi = A.nseg - 1;
+  while (lo < hi) {
+    const int32_t mid = (lo + hi + 1) >> 1;
+    if (segs[mid].flat0 <= f)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return (uint32_t)lo;
 }
 
 __device__ __forceinline__ uint32_t find_segment(const SampleLaunch& A, uint64_t f) {
@@ -176,7 +244,19 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   const int32_t* shash = nullptr;
   unsigned long long E = 0;
   int64_t lo_e = 0, hi_e = 0;
-  uint64_t cur = 0, cend = 0;
+  // the wave's current work chunk [cur, cend) and the segment of cur
+  // (wave-uniform); every refill hands out samples of one segment only, so
+  // the segment and its query are read with scalar loads, once per refill
+  uint64_t cur = 0, cend = 0, cseg_end = 0;
+  uint32_t cseg = 0;
+  // the current segment and its query (wave-uniform, refreshed when cur
+  // crosses a segment boundary)
+  uint64_t c_first = 0, c_flat0 = 0, c_out = 0;
+  uint32_t c_stream = 0, c_qid = 0, c_smask = 0;
+  int32_t c_k = 0, c_s0 = 0;
+  int64_t c_l = 0;
+  const TabGroup* c_tab = nullptr;
+  const int32_t* c_shash = nullptr;
   bool exhausted = false;
   uint32_t acc_seg = 0xFFFFFFFFu;
   unsigned long long acc_y = 0, acc_e = 0;
@@ -205,56 +285,73 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       acc_e += E;
       st = T_IDLE;
     }
-    // (1) idle lanes take the next samples of the wave's chunk
+    // (1) idle lanes take the next samples of the wave's chunk, all from the
+    // segment of `cur`
     const unsigned long long idle = __ballot(st == T_IDLE);
+    bool started = false;
     if (idle && !exhausted) {
-      const uint32_t want = (uint32_t)__popcll(idle);
-      const uint32_t rank = lane_prefix(idle);
-      uint32_t given = 0;
-      while (given < want) {
-        if (cur >= cend) {
-          unsigned long long c = 0;
-          if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
-          c = uniform64(__shfl(c, 0, 64));
-          if (c >= A.total) {
-            exhausted = true;
-            break;
-          }
+      if (cur >= cend) {
+        unsigned long long c = 0;
+        if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
+        c = uniform64(__shfl(c, 0, 64));
+        if (c >= A.total) {
+          exhausted = true;
+        } else {
           cur = c;
           cend = c + A.tiny_chunk < A.total ? c + A.tiny_chunk : A.total;
         }
-        const uint64_t room = cend - cur;
-        const uint32_t take = room < (uint64_t)(want - given) ? (uint32_t)room : want - given;
-        if (st == T_IDLE && rank >= given && rank < given + take) {
-          f = cur + (rank - given);
+      }
+      if (!exhausted) {
+        if (cur >= cseg_end) {
+          cseg = uniform(find_segment_uniform(A, cur));
+          const OI_CONST Segment* Sp = cptr(A.segs) + cseg;
+          c_flat0 = Sp->flat0;
+          c_first = Sp->first;
+          c_out = Sp->out_off;
+          c_stream = Sp->stream;
+          cseg_end = c_flat0 + Sp->count;
+          const OI_CONST QueryDev* Qp = cptr(A.qs) + Sp->q;
+          c_qid = Qp->qid;
+          c_l = Qp->l;
+          c_k = Qp->k;
+          c_s0 = Qp->s0;
+          c_smask = Qp->smask;
+          c_shash = Qp->shash;
+          c_tab = Qp->tab;
+        }
+        const uint64_t lim = cend < cseg_end ? cend : cseg_end;
+        const uint64_t room = lim - cur;
+        const uint32_t want = (uint32_t)__popcll(idle);
+        const uint32_t take = room < (uint64_t)want ? (uint32_t)room : want;
+        const uint32_t rank = lane_prefix(idle);
+        if (st == T_IDLE && rank < take) {
+          f = cur + rank;
           st = T_START;
+          started = true;
         }
         cur += take;
-        given += take;
       }
     }
     if (__ballot(st != T_IDLE) == 0ull) {
       if (exhausted) break;
       continue;
     }
-    // (2) new samples: locate them and copy their query's fields.  Long
+    // (2) new samples copy their (common) segment's and query's fields.  Long
     // Stage-1 tables (and, in the backward, samples known to be large) go
     // straight to the small kernel.
     bool pass_on = false;
-    if (st == T_START) {
-      sg = find_segment(A, f);
-      const Segment S = A.segs[sg];
-      stream = S.stream;
-      s = S.first + (f - S.flat0);
-      oidx = S.out_off + (f - S.flat0);
-      const QueryDev& Q = A.qs[S.q];
-      qid = Q.qid;
-      ql = Q.l;
-      qk = Q.k;
-      s0 = Q.s0;
-      smask = Q.smask;
-      shash = Q.shash;
-      tab = Q.tab;
+    if (started) {
+      sg = cseg;
+      stream = c_stream;
+      s = c_first + (f - c_flat0);
+      oidx = c_out + (f - c_flat0);
+      qid = c_qid;
+      ql = c_l;
+      qk = c_k;
+      s0 = c_s0;
+      smask = c_smask;
+      shash = c_shash;
+      tab = c_tab;
       pass_on = ql > (int64_t)TINY_LMAX;
       if (BWD) {
         y = A.y_in[oidx];
@@ -281,7 +378,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       tv[0] = vv.x; tv[1] = vv.y; tv[2] = vv.z; tv[3] = vv.w;
       tp[0] = pp.x; tp[1] = pp.y; tp[2] = pp.z; tp[3] = pp.w;
     } else if (st == T_STAGE1) {
-      const TabGroup T = tab[g];
+      const TabGroup T = load_tab(tab, g);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         tv[b] = T.v[b];
@@ -306,17 +403,18 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         st = T_EXPAND;
       }
     } else if (st == T_START) {
-      // Stage 1, lines 2-3 of Alg. 1
-      const QueryDev& Q = A.qs[A.segs[sg].q];
+      // Stage 1, lines 2-3 of Alg. 1 (a single entry is selected whatever U is)
       int64_t i = 0;
       if (ql > 1) {
+        const QueryDev& Q = A.qs[A.segs[sg].q];
+        const OI_GLOBAL double* cdf = gptr(Q.cdf);  // per-lane: lanes may hold samples of different segments
         const uint64_t a = d.w[0] >> 5, b = d.w[1] >> 6;
         const double U = (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
         const double t = U * Q.beta0;
         int64_t lo = 0, hi = ql;
         while (lo < hi) {
           const int64_t mid = lo + ((hi - lo) >> 1);
-          if (Q.cdf[mid + 1] > t)
+          if (cdf[mid + 1] > t)
             hi = mid;
           else
             lo = mid + 1;
@@ -325,7 +423,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         if (lo >= ql) {
           i = -1;
           for (int64_t j = ql - 1; j >= 0; --j)
-            if (Q.cdf[j + 1] > Q.cdf[j]) {
+            if (cdf[j + 1] > cdf[j]) {
               i = j;
               break;
             }
@@ -335,7 +433,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
           }
         }
       }
-      const int32_t vi = tab[i >> 2].v[i & 3];
+      const int32_t vi = tab_v(tab, i);
       vis[0] = vi;
       cnt = 1;
       qh = 0;
@@ -369,7 +467,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
               if (qk != 1) {
                 uint32_t h = mix32((uint32_t)tv[b]) & smask;
                 while (true) {
-                  const int32_t c = shash[h];
+                  const int32_t c = gptr(shash)[h];
                   if (c == tv[b]) {
                     ins = true;
                     break;
@@ -463,6 +561,15 @@ struct SmallLds {
   uint32_t s_y[K];
   int32_t s_vi[K];
   uint32_t s_i[K];
+  // the slot's query, copied when the sample starts
+  uint32_t s_full;  // slots whose LDS set overflowed (backward consistency check)
+  const TabGroup* s_tab[K];
+  const int32_t* s_shash[K];
+  int64_t s_l[K];
+  uint32_t s_qid[K];
+  uint32_t s_smask[K];
+  int32_t s_k[K];
+  int32_t s_s0[K];
   uint32_t head, tail;
 };
 
@@ -472,30 +579,55 @@ __device__ __forceinline__ uint32_t hslot(int32_t v) {
   return ((uint32_t)v * 0x9E3779B1u) >> (32 - LOG);
 }
 
+// Open addressing with linear probing; every probe loop is bounded by the
+// table size, so a full table can never make a lane spin.
 template <int HCAP>
 __device__ __forceinline__ bool hash_contains(const int32_t* h, int32_t v) {
   uint32_t p = hslot<HCAP>(v);
-  while (true) {
+  for (int n = 0; n < HCAP; ++n) {
     const int32_t c = h[p];
     if (c == v) return true;
     if (c < 0) return false;
     p = (p + 1) & (HCAP - 1);
   }
+  return false;
 }
 
+// 1: inserted, 0: already present, -1: table full
 template <int HCAP>
-__device__ __forceinline__ bool hash_insert(int32_t* h, int32_t v) {
+__device__ __forceinline__ int hash_insert(int32_t* h, int32_t v) {
   uint32_t p = hslot<HCAP>(v);
-  while (true) {
+  for (int n = 0; n < HCAP; ++n) {
     int32_t c = h[p];
-    if (c == v) return false;
+    if (c == v) return 0;
     if (c < 0) {
       c = atomicCAS(&h[p], -1, v);
-      if (c < 0) return true;
-      if (c == v) return false;
+      if (c < 0) return 1;
+      if (c == v) return 0;
     }
     p = (p + 1) & (HCAP - 1);
   }
+  return -1;
+}
+
+// Remove, in order, the ring items of the slots in `mask` (stable compaction
+// of [head, tail)).  Must be reached by the whole wave.
+template <int RCAP>
+__device__ void drop_ring_items(uint64_t* ring, uint32_t* head, uint32_t* tail, uint32_t mask, int lane) {
+  const uint32_t h0 = uniform(*head), n0 = uniform(*tail) - h0;
+  uint32_t w = h0;
+  for (uint32_t i0 = 0; i0 < n0; i0 += 64) {
+    const uint32_t i = i0 + lane;
+    const bool valid = i < n0;
+    const uint64_t it = valid ? ring[(h0 + i) & (RCAP - 1)] : 0ull;
+    const bool keep = valid && !((mask >> item_slot(it)) & 1u);
+    const unsigned long long bal = __ballot(keep);
+    wave_sync();
+    if (keep) ring[(w + lane_prefix(bal)) & (RCAP - 1)] = it;
+    w += (uint32_t)__popcll(bal);
+    wave_sync();
+  }
+  if (lane == 0) *tail = w;
 }
 
 template <int K, int HCAP, int RCAP, int R, bool BWD>
@@ -516,6 +648,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
   if (lane == 0) {
     W.head = 0;
     W.tail = 0;
+    W.s_full = 0;
   }
   wave_sync();
 
@@ -576,7 +709,14 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
             atomicOr(A.err, 1u);
             i = 0;
           }
-          const int32_t vi = Q.tab[i >> 2].v[i & 3];
+          const int32_t vi = tab_v(Q.tab, i);
+          W.s_tab[lane] = Q.tab;
+          W.s_shash[lane] = Q.shash;
+          W.s_l[lane] = Q.l;
+          W.s_qid[lane] = Q.qid;
+          W.s_smask[lane] = Q.smask;
+          W.s_k[lane] = Q.k;
+          W.s_s0[lane] = Q.s0;
           W.s_s[lane] = s;
           W.s_q[lane] = S.q;
           W.s_seg[lane] = sg;
@@ -606,8 +746,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         const int32_t vi = W.s_vi[lane];
         W.hash[lane][hslot<HCAP>(vi)] = vi;
         const uint32_t i = W.s_i[lane];
-        const QueryDev& Q = A.qs[W.s_q[lane]];
-        const bool more = (int64_t)i + 1 < Q.l;
+        const bool more = (int64_t)i + 1 < W.s_l[lane];
         const uint32_t pos = atomicAdd(&W.tail, more ? 2u : 1u);
         W.ring[pos & (RCAP - 1)] = mk_item(lane, ITEM_NODE, 0, (uint32_t)vi);
         if (more) W.ring[(pos + 1) & (RCAP - 1)] = mk_item(lane, ITEM_STAGE1, 0, i + 1);
@@ -649,11 +788,11 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
           ntask = (uint32_t)((ee + 3) >> 2) - g0;
         }
       } else {
-        const QueryDev& Q = A.qs[W.s_q[slot]];
+        const int64_t l = W.s_l[slot];
         eb = a;
-        ee = Q.l;
+        ee = l;
         g0 = a >> 2;
-        ntask = (uint32_t)((Q.l + 3) >> 2) - g0;
+        ntask = (uint32_t)((l + 3) >> 2) - g0;
       }
     }
     const uint32_t sc = wave_incl_scan(ntask, lane);
@@ -717,14 +856,17 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         const uint32_t base = lo ? W.it_scan[lo - 1] : 0u;
         const uint32_t g = W.it_g0[lo] + (t - base);
         const int64_t lo_e = W.it_eb[lo], hi_e = W.it_ee[lo];
-        const QueryDev& Q = A.qs[W.s_q[sl]];
+        const uint32_t qid = W.s_qid[sl];
+        const int32_t qk = W.s_k[sl], qs0 = W.s_s0[sl];
+        const uint32_t qmask = W.s_smask[sl];
+        const int32_t* qhash = W.s_shash[sl];
         const uint64_t s = W.s_s[sl];
         const uint32_t stream = W.s_stream[sl];
         const int32_t* hs = W.hash[sl];
         tslot[r] = sl;
         uint32_t mk = 0;
         if (kd == ITEM_NODE) {
-          const Words d = philox_draw(Q.qid, A.seed, KIND_EDGE, stream, s, g);
+          const Words d = philox_draw(qid, A.seed, KIND_EDGE, stream, s, g);
           const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
           const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
           const int32_t va[4] = {vv.x, vv.y, vv.z, vv.w};
@@ -736,19 +878,20 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
             if (e >= lo_e && e < hi_e) {
               const bool live = edge_live(d.w[b], pa[b]);
               if (BWD) {
-                if (!in_seed_set(Q, va[b])) {
+                if (!in_seed_fields(qk, qs0, qmask, qhash, va[b])) {
                   const unsigned long long y = W.s_y[sl];
                   atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
                   if (live && !hash_contains<HCAP>(hs, va[b])) mk |= 1u << b;
                 }
-              } else if (live && !in_seed_set(Q, va[b]) && !hash_contains<HCAP>(hs, va[b])) {
+              } else if (live && !in_seed_fields(qk, qs0, qmask, qhash, va[b]) &&
+                         !hash_contains<HCAP>(hs, va[b])) {
                 mk |= 1u << b;
               }
             }
           }
         } else {
-          const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, stream, s, g);
-          const TabGroup T = Q.tab[g];
+          const Words d = philox_draw(qid, A.seed, KIND_STAGE1, stream, s, g);
+          const TabGroup T = load_tab(W.s_tab[sl], g);
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int64_t j = 4 * (int64_t)g + b;
@@ -766,11 +909,9 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
     wave_sync();
 
     // ---- hand over samples that would outgrow the LDS set ----------------
-    // (In the backward every started sample has Y <= CMAX, so this can only
-    // trigger if y_in disagrees with the recomputation: flag it and drop the
-    // sample rather than overfill the set.)
+    // (forward only: in the backward every started sample is known to fit)
     uint32_t defmask = 0;
-    {
+    if (!BWD) {
 #pragma unroll
       for (int k = 0; k < K; ++k) {
         if (uniform(W.s_active[k]) && uniform(W.s_cnt[k]) + uniform(W.s_new[k]) > CMAX) defmask |= 1u << k;
@@ -779,31 +920,13 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         if (lane == 0) {
           for (int k = 0; k < K; ++k) {
             if ((defmask >> k) & 1u) {
-              if (BWD) {
-                atomicOr(A.err, 8u);
-              } else {
-                const unsigned int pos = atomicAdd(A.nlist2, 1u);
-                A.list2[pos] = W.s_f[k];
-              }
+              const unsigned int pos = atomicAdd(A.nlist2, 1u);
+              A.list2[pos] = W.s_f[k];
               W.s_active[k] = 0;
             }
           }
         }
-        // drop the handed-over slots' items from the ring (stable compaction)
-        const uint32_t h0 = uniform(W.head), n0 = uniform(W.tail) - h0;
-        uint32_t w = h0;
-        for (uint32_t i0 = 0; i0 < n0; i0 += 64) {
-          const uint32_t i = i0 + lane;
-          const bool valid = i < n0;
-          const uint64_t it = valid ? W.ring[(h0 + i) & (RCAP - 1)] : 0ull;
-          const bool keep = valid && !((defmask >> item_slot(it)) & 1u);
-          const unsigned long long bal = __ballot(keep);
-          wave_sync();
-          if (keep) W.ring[(w + lane_prefix(bal)) & (RCAP - 1)] = it;
-          w += (uint32_t)__popcll(bal);
-          wave_sync();
-        }
-        if (lane == 0) W.tail = w;
+        drop_ring_items<RCAP>(W.ring, &W.head, &W.tail, defmask, lane);
       }
     }
     if (lane < K) W.s_new[lane] = 0;
@@ -818,17 +941,36 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         for (int b = 0; b < 4; ++b) {
           if ((mask[r] >> b) & 1u) {
             const int32_t v = tv[r][b];
-            if (hash_insert<HCAP>(W.hash[sl], v)) {
+            const int ins = hash_insert<HCAP>(W.hash[sl], v);
+            if (ins > 0) {
               atomicAdd(&W.s_cnt[sl], 1u);
               atomicAdd(&W.s_pend[sl], 1u);
               const uint32_t pos = atomicAdd(&W.tail, 1u);
               W.ring[pos & (RCAP - 1)] = mk_item(sl, ITEM_NODE, 0, (uint32_t)v);
+            } else if (ins < 0) {
+              atomicOr(&W.s_full, 1u << sl);
             }
           }
         }
       }
     }
     wave_sync();
+
+    // ---- a full set can only mean that y_in disagrees with the recomputed
+    // sample (backward): flag it and drop the sample
+    {
+      const uint32_t full = uniform(W.s_full);
+      if (full) {
+        if (lane == 0) {
+          atomicOr(A.err, 8u);
+          for (int k = 0; k < K; ++k)
+            if ((full >> k) & 1u) W.s_active[k] = 0;
+          W.s_full = 0;
+        }
+        drop_ring_items<RCAP>(W.ring, &W.head, &W.tail, full, lane);
+        wave_sync();
+      }
+    }
 
     // ---- finished samples --------------------------------------------------
 #pragma unroll
@@ -923,7 +1065,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         atomicOr(A.err, 1u);
         i = 0;
       }
-      const int32_t vi = Q.tab[i >> 2].v[i & 3];
+      const int32_t vi = tab_v(Q.tab, i);
       queue[0] = vi;
       atomicOr(&bits[vi >> 5], 1u << (vi & 31));
       s_tail = 1;
@@ -937,7 +1079,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
     const int64_t gend = (Q.l + 3) >> 2;
     for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += LB) {
       const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
-      const TabGroup T = Q.tab[g];
+      const TabGroup T = load_tab(Q.tab, g);
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
         const int64_t j = 4 * g + b;
@@ -1198,6 +1340,18 @@ __global__ void __launch_bounds__(256) bwd_stage1_kernel(const EdgeGroup* eg, co
   }
 }
 
+// p_e = sigmoid(theta_e) in fp64, rounded to fp32, written into the edge
+// groups and into a plain fp32 array.
+__global__ void __launch_bounds__(256) theta_to_p_kernel(const float* theta, int64_t m, EdgeGroup* eg, float* p_out) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+    const double t = (double)theta[e];
+    const float p = (float)(1.0 / (1.0 + exp(-t)));
+    eg[e >> 2].p[e & 3] = p;
+    p_out[e] = p;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host-callable launchers
 // ---------------------------------------------------------------------------
@@ -1288,6 +1442,14 @@ hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64
 }
 
 size_t pair_seg_size() { return sizeof(PairSeg); }
+
+hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float* p_out, hipStream_t st) {
+  if (m == 0) return hipSuccess;
+  int64_t blocks = (m + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(theta_to_p_kernel, dim3((unsigned)blocks), dim3(256), 0, st, theta, m, eg, p_out);
+  return hipGetLastError();
+}
 
 hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L,
                             const unsigned long long* D, double scale, int theta, float* grad, hipStream_t st) {

@@ -32,6 +32,7 @@ hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, uns
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
                           hipStream_t st);
 size_t pair_seg_size();
+hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float* p_out, hipStream_t st);
 hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L, const unsigned long long* D,
                             double scale, int theta, float* grad, hipStream_t st);
 hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
@@ -108,7 +109,7 @@ struct oi_graph {
   int variant = 0;
   bool use_tiny = true;
   uint32_t chunk = 256;
-  uint32_t tiny_chunk = 1024;
+  uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
   uint64_t round_max = 1ull << 26;
   // timing
   bool timing = false;
@@ -331,6 +332,10 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
     if (bpc < 1) bpc = 1;
     const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
+    if (g->tiny_chunk == 0) {
+      const uint64_t c = total / ((uint64_t)blocks * 4 * 8);
+      A.tiny_chunk = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(256, c));
+    }
     HIP_TRY(oi::launch_tiny(is_bwd, A, blocks, g->stream));
   }
   if (g->timing) HIP_TRY(hipEventRecord(g->ev[1], g->stream));
@@ -814,6 +819,32 @@ oi_status oi_graph_set_probs(oi_graph* g, const float* p, int device_ptr) {
   return upload_graph(g);
 }
 
+oi_status oi_graph_set_theta(oi_graph* g, const float* theta, int device_ptr) {
+  if (!g || (g->m > 0 && !theta)) return fail(OI_EINVAL, "null argument");
+  if (g->m == 0) return OI_OK;
+  DevBuf dt, dp;
+  const float* th = theta;
+  if (!device_ptr) {
+    HIP_TRY(dt.ensure((size_t)g->m * 4));
+    HIP_TRY(hipMemcpy(dt.p, theta, (size_t)g->m * 4, hipMemcpyHostToDevice));
+    th = dt.as<float>();
+  }
+  HIP_TRY(dp.ensure((size_t)g->m * 4));
+  HIP_TRY(oi::launch_theta_to_p(th, g->m, g->d_eg.as<oi::EdgeGroup>(), dp.as<float>(), g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  // the host copy feeds the Stage-1 tables
+  HIP_TRY(hipMemcpy(g->p.data(), dp.p, (size_t)g->m * 4, hipMemcpyDeviceToHost));
+  for (float x : g->p)
+    if (!(x >= 0.0f && x <= 1.0f)) return fail(OI_EINVAL, "theta gave a probability outside [0, 1]");
+  return OI_OK;
+}
+
+oi_status oi_graph_get_probs(oi_graph* g, float* p_out) {
+  if (!g || (g->m > 0 && !p_out)) return fail(OI_EINVAL, "null argument");
+  std::copy(g->p.begin(), g->p.end(), p_out);
+  return OI_OK;
+}
+
 oi_status oi_set_stream(oi_graph* g, void* hip_stream) {
   if (!g) return fail(OI_EINVAL, "null graph");
   g->stream = (hipStream_t)hip_stream;
@@ -997,7 +1028,7 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
   if (variant >= 0) g->variant = variant;
   if (chunk > 0) g->chunk = (uint32_t)chunk;
   if (tiny >= 0) g->use_tiny = tiny != 0;
-  if (tiny_chunk > 0) g->tiny_chunk = (uint32_t)tiny_chunk;
+  if (tiny_chunk >= 0) g->tiny_chunk = (uint32_t)tiny_chunk;
   if (round_max > 0) {
     if (round_max % kChunk) return fail(OI_EINVAL, "round_max must be a multiple of 4096");
     if (round_max > (1ll << 31)) return fail(OI_ERANGE, "round_max above 2^31");
