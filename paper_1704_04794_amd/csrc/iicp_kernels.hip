@@ -207,6 +207,37 @@ __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
   return x;
 }
 
+// Sum of a 64-bit value over the 64 lanes of the wave (every lane gets it).
+__device__ __forceinline__ unsigned long long wave_sum64(unsigned long long x) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) x += __shfl_xor(x, d, 64);
+  return x;
+}
+
+// Add the per-lane (segment, Y sum, E sum) accumulators of the lanes with
+// `pred` to seg_sums and to the tier's two totals, one atomic per distinct
+// segment in the wave rather than one per lane: same-address atomics from
+// every lane of every wave serialise at the memory side.  Must be reached by
+// the whole wave.
+__device__ __forceinline__ void wave_flush(bool pred, uint32_t seg, unsigned long long y, unsigned long long e,
+                                           unsigned long long* seg_sums, unsigned long long* tier, int lane) {
+  unsigned long long todo = __ballot(pred);
+  while (todo) {
+    const int leader = __builtin_ctzll(todo);
+    const uint32_t sq = uniform((uint32_t)__shfl((int)seg, leader, 64));
+    const bool mine = pred && seg == sq;
+    const unsigned long long sy = wave_sum64(mine ? y : 0ull);
+    const unsigned long long se = wave_sum64(mine ? e : 0ull);
+    if (lane == leader) {
+      atomicAdd(&seg_sums[2 * sq], sy);
+      atomicAdd(&seg_sums[2 * sq + 1], se);
+      atomicAdd(&tier[0], sy);
+      atomicAdd(&tier[1], se);
+    }
+    todo &= ~__ballot(mine);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // tiny_kernel: one sample per lane
 // ---------------------------------------------------------------------------
@@ -262,7 +293,11 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   unsigned long long acc_y = 0, acc_e = 0;
 
   while (true) {
-    // (0) lanes whose queue is drained finish their sample
+    // (0) lanes whose queue is drained finish their sample.  A lane whose
+    // sample belongs to another segment than its running sums flushes them
+    // first; lanes reach segment ends at different times, so these atomics
+    // rarely meet on one address (the final flush, where they would, is
+    // wave-cooperative)
     if (st == T_POP && qh == cnt) {
       if (BWD) {
         if (cnt != y) atomicOr(A.err, 2u);
@@ -514,12 +549,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     }
     hand_over(pass_on, f, A.list1, A.nlist1, lane);
   }
-  if (acc_seg != 0xFFFFFFFFu) {
-    atomicAdd(&A.seg_sums[2 * acc_seg], acc_y);
-    atomicAdd(&A.seg_sums[2 * acc_seg + 1], acc_e);
-    atomicAdd(&A.tier_sums[0], acc_y);
-    atomicAdd(&A.tier_sums[1], acc_e);
-  }
+  wave_flush(acc_seg != 0xFFFFFFFFu, acc_seg, acc_y, acc_e, A.seg_sums, A.tier_sums, lane);
 }
 
 // ---------------------------------------------------------------------------
