@@ -45,7 +45,7 @@ def cpu_baseline(g, S, seconds):
     t = time.perf_counter()
     O.sample_fixed(g, S, 0, RUN_SEED, 0, 0, n0, want_y=False, nthreads=nt)
     rate0 = n0 / max(time.perf_counter() - t, 1e-6)
-    N = int(min(max(rate0 * seconds, n0), 5e8))
+    N = int(min(max(rate0 * seconds, n0), 2e10))
     log(f"cpu baseline: {N} samples on {nt} threads (calibrated {rate0:.3g}/s)")
     t = time.perf_counter()
     r = O.sample_fixed(g, S, 0, RUN_SEED, 0, 0, N, want_y=False, nthreads=nt)
@@ -53,6 +53,48 @@ def cpu_baseline(g, S, seconds):
     return {"value": N / dt, "unit": "samples/s", "cores": nt, "kind": "oracle",
             "sample": f"IICP samples 0..{N - 1} of stream X of the same query (fixed count, oracle in C, "
                       f"{nt} threads), {dt:.1f} s; GTEPS {r['sum_e'] / dt / 1e9:.4f}"}
+
+
+def gather_roofline(G, count=1 << 26, reps=3):
+    """Best of `reps` runs of the library's random-gather probe on the same
+    graph: the samplers' row_ptr + edge-group reads without coins or visited
+    sets, i.e. the random-read bandwidth the sampling kernels are bound by."""
+    best = None
+    for r in range(reps):
+        x = G.gather_probe(count, seed=r)
+        if best is None or x["gbps"] > best["gbps"]:
+            best = x
+    return best
+
+
+def backward_ratio(P, N=1_000_000, reps=5):
+    """Time of oi_backward over N samples (reusing the forward's Y) over the
+    time of oi_sample_fixed over the same N, on the 1M-node sigmoid(theta)
+    workload with |S| = 50."""
+    import torch
+
+    from oi_inputs import make_config
+    g, sets, extra = make_config("cl1m_sig")
+    S = sets[0]
+    G = P.Graph.from_inputs(g)
+    grad = torch.empty(g.m, dtype=torch.float32, device="cuda")
+    y, _, _ = G.sample_fixed(S, N)
+    G.backward(S, N, grad, y_in=y)
+    torch.cuda.synchronize()
+    tf = tb = float("inf")
+    for _ in range(reps):
+        t = time.perf_counter()
+        y, _, r = G.sample_fixed(S, N)
+        torch.cuda.synchronize()
+        tf = min(tf, time.perf_counter() - t)
+        t = time.perf_counter()
+        G.backward(S, N, grad, y_in=y)
+        torch.cuda.synchronize()
+        tb = min(tb, time.perf_counter() - t)
+    G.close()
+    return {"workload": "cl1m_sig: Chung-Lu n=1e6 m~1e7 gamma=2.1, p=sigmoid(theta), theta~N(-3,1), |S|=50",
+            "samples": N, "forward_ms": tf * 1e3, "backward_ms": tb * 1e3, "ratio": tb / tf,
+            "note": "wall time per call incl. host work, best of %d; backward reuses the forward's Y" % reps}
 
 
 def batched_vs_single(P, args):
@@ -103,6 +145,7 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward", action="store_true", help="skip the backward/forward ratio")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--workload", choices=("cl1m", "cl4m"), default="cl1m",
@@ -198,7 +241,13 @@ def main():
         "sampler": {k: tm[k] for k in ("tiny_ms", "small_ms", "large_ms", "samples", "handed_small",
                                        "handed_large", "tiny_y", "small_y", "large_y")},
     }
+    gr = gather_roofline(G)
+    out["roofline"]["measured_gather_gbps"] = gr["gbps"]
+    out["roofline"]["frac_of_measured_gather"] = achieved / gr["gbps"] if gr["gbps"] > 0 else None
+    out["roofline"]["gather_probe"] = {"nodes": 1 << 26, "edges": gr["edges"], "ms": gr["ms"]}
     G.close()
+    if not args.no_backward:
+        out["backward"] = backward_ratio(P)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, S, args.cpu_seconds)
     print(json.dumps(out), flush=True)

@@ -194,6 +194,21 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
 int oi_num_variants(void);
 oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* ring_cap, int* rounds_per_pass);
 
+/* Measurement aid, outside the method: the random-gather bandwidth that the
+ * samplers' Stage-2 reads (Alg. 1, the BFS over out-edges) are bound by, on
+ * this graph.  For `count` nodes u, each the target of a uniformly random
+ * edge h(seed, i) (a choice in proportion to in-degree, the law by which
+ * cascades reach nodes), one GPU lane reads row_ptr[u], row_ptr[u+1] and
+ * then u's out-edge targets and probabilities in the same 32-byte groups of
+ * four edges that the samplers read; there are no coins, queues or visited
+ * sets.  Outputs: useful_bytes = 16 * count + 8 * edges (the samplers'
+ * algorithmic bytes per activated node and per examined edge), edges = the
+ * out-edges read, ms = kernel time (HIP events on the graph's stream).  The
+ * node list (4 * count bytes) is allocated and freed inside the call.
+ * count in [1, 2^31], else OI_ERANGE; a graph with m = 0 gives OI_EINVAL. */
+oi_status oi_gather_probe(oi_graph* g, uint64_t count, uint32_t seed, uint64_t* useful_bytes, uint64_t* edges,
+                          double* ms);
+
 const char* oi_last_error(void);
 
 #ifdef __cplusplus

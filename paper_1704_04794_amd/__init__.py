@@ -9,7 +9,7 @@ from __future__ import annotations
 import numpy as np
 
 from ._binding import (  # noqa: F401
-    LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_backward,
+    LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_backward, oi_gather_probe,
     oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
     oi_graph_set_theta, oi_last_error,
     oi_num_variants, oi_sample_fixed, oi_set_stream, oi_set_tuning, oi_stage1_table, oi_timing_enable,
@@ -96,6 +96,11 @@ class Graph:
                  query_id=0, run_seed=RUN_SEED):
         oi_backward(self.h, query_id, seeds, first, count, run_seed, y_in, param, grad_scale, grad_out)
         return grad_out
+
+    def gather_probe(self, count, seed=0):
+        """Random-read bandwidth of this graph's CSR under the samplers' access
+        pattern (no coins or visited sets): dict(useful_bytes, edges, ms, gbps)."""
+        return oi_gather_probe(self.h, count, seed)
 
     def timing(self, enable=None):
         if enable is not None:

@@ -60,6 +60,10 @@ class OiError(RuntimeError):
 def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is missing: build it with `python -m paper_1704_04794_amd.build`")
+    # torch first: its HIP runtime is then the one the library binds to, so a
+    # process has a single runtime, and device pointers and streams pass
+    # between torch and the library unchanged
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     i64, u64, u32, i32, dbl, vp, ci = C.c_int64, C.c_uint64, C.c_uint32, C.c_int32, C.c_double, C.c_void_p, C.c_int
     P = C.POINTER
@@ -78,6 +82,7 @@ def _load():
         "oi_timing_get": [vp, P(oi_timing)],
         "oi_set_tuning": [vp, ci, ci, ci, ci, i64],
         "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
+        "oi_gather_probe": [vp, u64, u32, P(u64), P(u64), P(dbl)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -241,3 +246,12 @@ def oi_variant_info(v):
     a, b, c, d = C.c_int(), C.c_int(), C.c_int(), C.c_int()
     _check("oi_variant_info", _lib.oi_variant_info(int(v), C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
     return dict(slots_per_wave=a.value, hash_cap=b.value, ring_cap=c.value, rounds_per_pass=d.value)
+
+
+def oi_gather_probe(g, count, seed=0):
+    """Random-gather bandwidth probe: dict(useful_bytes, edges, ms, gbps)."""
+    b, e, t = C.c_uint64(), C.c_uint64(), C.c_double()
+    _check("oi_gather_probe", _lib.oi_gather_probe(g, int(count), int(seed) & 0xFFFFFFFF, C.byref(b), C.byref(e),
+                                                   C.byref(t)))
+    return dict(useful_bytes=b.value, edges=e.value, ms=t.value,
+                gbps=b.value / (t.value * 1e-3) / 1e9 if t.value > 0 else 0.0)

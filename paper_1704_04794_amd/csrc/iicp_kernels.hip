@@ -1383,6 +1383,92 @@ __global__ void __launch_bounds__(256) theta_to_p_kernel(const float* theta, int
 }
 
 // ---------------------------------------------------------------------------
+// gather probe: the samplers' memory accesses without coins, queues or
+// visited sets, to measure the random-read bandwidth they are bound by
+// ---------------------------------------------------------------------------
+
+// nodes[i] = target of edge h(seed, i) mod m: nodes drawn in proportion to
+// their in-degree, the law by which a cascade reaches them.
+__global__ void __launch_bounds__(256) probe_nodes_kernel(const EdgeGroup* eg, int64_t m, uint64_t count,
+                                                          uint32_t seed, int32_t* nodes) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const uint32_t a = mix32((uint32_t)i ^ seed);
+    const uint32_t b = mix32((uint32_t)(i >> 32) ^ a ^ 0x85EBCA6Bu);
+    const uint64_t h = ((((uint64_t)b) << 32) | a) % (uint64_t)m;
+    nodes[i] = eg[h >> 2].v[h & 3];
+  }
+}
+
+// A wave takes 64 nodes, one per lane: each lane reads its node's row_ptr
+// pair, then the wave reads the edge groups of all 64 rows together, lane t
+// taking group t of the concatenated rows (so long rows are read by many
+// lanes and short ones do not leave lanes idle).  This reads exactly the
+// bytes the samplers read for those nodes, as fast as a wave can.
+// out[0] += edges read (inside the rows), out[1] ^= a fold of everything
+// read (keeps the loads live).
+__global__ void __launch_bounds__(256) gather_probe_kernel(const int64_t* row_ptr, const EdgeGroup* eg,
+                                                           const int32_t* nodes, uint64_t count,
+                                                           unsigned long long* out) {
+  __shared__ int64_t s_b[4][64], s_e[4][64];
+  __shared__ uint32_t s_end[4][64];
+  __shared__ unsigned long long red[4];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const uint64_t nwaves = (uint64_t)gridDim.x * 4;
+  uint64_t edges = 0;
+  uint32_t fold = 0;
+  for (uint64_t base = ((uint64_t)blockIdx.x * 4 + w) * 64; base < count; base += nwaves * 64) {
+    const uint64_t i = base + lane;
+    int64_t b = 0, e = 0;
+    if (i < count) {
+      const int32_t u = nodes[i];
+      b = row_ptr[u];
+      e = row_ptr[u + 1];
+    }
+    edges += (uint64_t)(e - b);
+    const uint32_t ng = e > b ? (uint32_t)(((e + 3) >> 2) - (b >> 2)) : 0u;
+    const uint32_t incl = wave_incl_scan(ng, lane);
+    s_b[w][lane] = b;
+    s_e[w][lane] = e;
+    s_end[w][lane] = incl;
+    wave_sync();
+    const uint32_t total = uniform((uint32_t)__shfl((int)incl, 63, 64));
+    for (uint32_t t = lane; t < total; t += 64) {
+      int lo = 0, hi = 63;  // first lane whose rows end after group t
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (s_end[w][mid] > t)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      const uint32_t start = lo ? s_end[w][lo - 1] : 0u;
+      const int64_t rb = s_b[w][lo], re = s_e[w][lo];
+      const int64_t g = (rb >> 2) + (int64_t)(t - start);
+      const OI_GLOBAL char* q = (const OI_GLOBAL char*)(gptr(eg) + g);
+      const v4i32 vv = *(const OI_GLOBAL v4i32*)q;
+      const v4i32 pp = *(const OI_GLOBAL v4i32*)(q + 16);
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t x = 4 * g + k;
+        if (x >= rb && x < re) fold ^= (uint32_t)vv[k] ^ (uint32_t)pp[k];
+      }
+    }
+    wave_sync();
+  }
+  const unsigned long long se = wave_sum64(edges);
+  unsigned long long sf = fold;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) sf ^= __shfl_xor(sf, d, 64);
+  if (lane == 0) red[w] = se;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(&out[0], red[0] + red[1] + red[2] + red[3]);
+    atomicXor(&out[1], sf);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // host-callable launchers
 // ---------------------------------------------------------------------------
 struct SmallVariant {
@@ -1498,6 +1584,30 @@ hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const i
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(bwd_stage1_kernel, dim3((unsigned)blocks), dim3(256), 0, st, eg, se_off, se, P, l, acc_tab,
                      sumY, scale, theta, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_nodes(const EdgeGroup* eg, int64_t m, uint64_t count, uint32_t seed, int32_t* nodes,
+                              hipStream_t st) {
+  if (count == 0 || m == 0) return hipSuccess;
+  uint64_t blocks = (count + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(probe_nodes_kernel, dim3((unsigned)blocks), dim3(256), 0, st, eg, m, count, seed, nodes);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, const int32_t* nodes, uint64_t count,
+                               unsigned long long* out, int cus, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  int bpc = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &bpc, reinterpret_cast<const void*>(&gather_probe_kernel), 256, 0);
+  if (e != hipSuccess) return e;
+  if (bpc < 1) bpc = 1;
+  uint64_t blocks = (uint64_t)bpc * (uint64_t)cus;
+  const uint64_t need = (count + 255) / 256;
+  if (blocks > need) blocks = need;
+  hipLaunchKernelGGL(gather_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row_ptr, eg, nodes, count, out);
   return hipGetLastError();
 }
 

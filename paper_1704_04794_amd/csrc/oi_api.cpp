@@ -33,6 +33,10 @@ hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64
                           hipStream_t st);
 size_t pair_seg_size();
 hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float* p_out, hipStream_t st);
+hipError_t launch_probe_nodes(const EdgeGroup* eg, int64_t m, uint64_t count, uint32_t seed, int32_t* nodes,
+                              hipStream_t st);
+hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, const int32_t* nodes, uint64_t count,
+                               unsigned long long* out, int cus, hipStream_t st);
 hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L, const unsigned long long* D,
                             double scale, int theta, float* grad, hipStream_t st);
 hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
@@ -755,6 +759,42 @@ oi_status validate_probs(const std::vector<float>& p) {
 // C ABI
 // ===========================================================================
 extern "C" {
+
+oi_status oi_gather_probe(oi_graph* g, uint64_t count, uint32_t seed, uint64_t* useful_bytes, uint64_t* edges,
+                          double* ms) {
+  if (!g || !useful_bytes || !edges || !ms) return fail(OI_EINVAL, "null argument");
+  if (count == 0 || count > (1ull << 31)) return fail(OI_ERANGE, "count must be in [1, 2^31]");
+  if (g->m == 0) return fail(OI_EINVAL, "graph has no edges");
+  DevBuf nodes, out;
+  HIP_TRY(nodes.ensure(count * sizeof(int32_t)));
+  HIP_TRY(out.ensure(2 * sizeof(unsigned long long)));
+  HIP_TRY(hipMemsetAsync(out.p, 0, 2 * sizeof(unsigned long long), g->stream));
+  HIP_TRY(oi::launch_probe_nodes(g->d_eg.as<oi::EdgeGroup>(), g->m, count, seed, nodes.as<int32_t>(), g->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(OI_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(he));
+  }
+  he = hipEventRecord(e0, g->stream);
+  if (he == hipSuccess)
+    he = oi::launch_gather_probe(g->d_row_ptr.as<int64_t>(), g->d_eg.as<oi::EdgeGroup>(), nodes.as<int32_t>(), count,
+                                 out.as<unsigned long long>(), g->cus, g->stream);
+  if (he == hipSuccess) he = hipEventRecord(e1, g->stream);
+  if (he == hipSuccess) he = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+  unsigned long long h[2] = {0, 0};
+  if (he == hipSuccess) he = hipMemcpy(h, out.p, sizeof(h), hipMemcpyDeviceToHost);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (he != hipSuccess) return fail(OI_EHIP, std::string("gather probe failed: ") + hipGetErrorString(he));
+  *edges = h[0];
+  *useful_bytes = 16ull * count + 8ull * h[0];
+  *ms = (double)t;
+  return OI_OK;
+}
 
 const char* oi_last_error(void) { return g_err.c_str(); }
 

@@ -69,3 +69,14 @@ def test_variants_are_described():
         assert 2 * cmax <= info["hash_cap"]
     with pytest.raises(P.OiError):
         P.oi_variant_info(nv)
+
+
+def test_null_handles_are_rejected():
+    """Entry points given no graph fail with OI_EINVAL instead of touching a GPU."""
+    import paper_1704_04794_amd as P
+    for call in (lambda: P.oi_gather_probe(None, 1024),
+                 lambda: P.oi_timing_get(None),
+                 lambda: P.oi_set_tuning(None, 0)):
+        with pytest.raises(P.OiError) as ei:
+            call()
+        assert ei.value.status == P._binding.OI_EINVAL
