@@ -1048,7 +1048,15 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
 // ---------------------------------------------------------------------------
 // large_kernel: one block per handed-over sample, global bitmap + queue
 // ---------------------------------------------------------------------------
-constexpr int LB = 256;
+// A block of LB threads runs one sample at a time, taking samples from a
+// work counter.  The visited set is a bitmap of n bits and the queue an array
+// of n node ids, both owned by the block; the seed set is marked in the
+// bitmap while the sample runs, so an edge into S is never pushed.  Stage 2
+// expands the queue in batches of up to LB nodes: each thread reads one
+// node's row bounds, a block scan lays the batch's edge groups out in one
+// index space, and thread t takes groups t, t + LB, ... of it.  After the
+// sample the bits it set (the queue and S) are cleared again.
+constexpr int LB = 1024;
 
 __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, int tid, uint32_t* total) {
   const int lane = tid & 63, wid = tid >> 6;
@@ -1067,6 +1075,34 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, 
   return x + add;
 }
 
+// Sets (set = true) or clears the bits of the seed set in a block's bitmap.
+__device__ __forceinline__ void mark_seed_set(const QueryDev& Q, uint32_t* bits, bool set, int tid) {
+  if (Q.k == 1) {
+    if (tid == 0) {
+      if (set)
+        atomicOr(&bits[Q.s0 >> 5], 1u << (Q.s0 & 31));
+      else
+        atomicAnd(&bits[Q.s0 >> 5], ~(1u << (Q.s0 & 31)));
+    }
+    return;
+  }
+  for (uint32_t h = tid; h <= Q.smask; h += LB) {
+    const int32_t v = gptr(Q.shash)[h];
+    if (v >= 0) {
+      if (set)
+        atomicOr(&bits[v >> 5], 1u << (v & 31));
+      else
+        atomicAnd(&bits[v >> 5], ~(1u << (v & 31)));
+    }
+  }
+}
+
+// Marks v visited; true if this call was the first to do so.
+__device__ __forceinline__ bool claim(uint32_t* bits, int32_t v) {
+  const uint32_t bit = 1u << (v & 31);
+  return !(atomicOr(&bits[v >> 5], bit) & bit);
+}
+
 template <bool BWD>
 __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_tail;
@@ -1077,11 +1113,16 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
   __shared__ int64_t it_ee[LB];
   __shared__ uint32_t it_g0[LB];
   __shared__ int64_t s_i;
+  __shared__ uint32_t s_di;
   const int tid = threadIdx.x;
   uint32_t* bits = A.bits + (int64_t)blockIdx.x * A.bits_words;
   int32_t* queue = A.queue + (int64_t)blockIdx.x * A.n;
   const uint32_t nd = *A.nlist2;
-  for (uint32_t di = blockIdx.x; di < nd; di += gridDim.x) {
+  while (true) {
+    if (tid == 0) s_di = (uint32_t)atomicAdd(A.counter2, 1ull);
+    __syncthreads();
+    const uint32_t di = s_di;
+    if (di >= nd) break;
     const uint64_t f = A.list2[di];
     const uint32_t sg = find_segment(A, f);
     const Segment S = A.segs[sg];
@@ -1089,6 +1130,8 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
     const uint64_t s = S.first + (f - S.flat0);
     const uint64_t oidx = S.out_off + (f - S.flat0);
     const unsigned long long y = BWD ? A.y_in[oidx] : 0ull;
+    mark_seed_set(Q, bits, true, tid);
+    __syncthreads();
     if (tid == 0) {
       int64_t i = select_entry(Q, A.seed, S.stream, s);
       if (i < 0) {
@@ -1105,7 +1148,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
     }
     __syncthreads();
     const int64_t i = s_i;
-    // Stage 1, lines 4-6
+    // Stage 1, lines 4-6 of Alg. 1
     const int64_t gend = (Q.l + 3) >> 2;
     for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += LB) {
       const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
@@ -1115,9 +1158,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         const int64_t j = 4 * g + b;
         if (j > i && j < Q.l && (uint64_t)d.w[b] < T.thr[b]) {
           if (BWD) atomicAdd(&A.acc_tab[j], y);
-          const int32_t v = T.v[b];
-          const uint32_t bit = 1u << (v & 31);
-          if (!(atomicOr(&bits[v >> 5], bit) & bit)) queue[atomicAdd(&s_tail, 1u)] = v;
+          if (claim(bits, T.v[b])) queue[atomicAdd(&s_tail, 1u)] = T.v[b];
         }
       }
     }
@@ -1161,28 +1202,24 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         const uint32_t g = it_g0[lo] + (t - base);
         const int64_t lo_e = it_eb[lo], hi_e = it_ee[lo];
         const Words d = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, g);
-        const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
-        const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
-        const int32_t va[4] = {vv.x, vv.y, vv.z, vv.w};
-        const float pa[4] = {pp.x, pp.y, pp.z, pp.w};
+        const OI_GLOBAL char* q = (const OI_GLOBAL char*)(gptr(A.eg) + g);
+        const v4i32 va = *(const OI_GLOBAL v4i32*)q;
+        const v4i32 pa = *(const OI_GLOBAL v4i32*)(q + 16);
+        const float pb[4] = {__int_as_float(pa.x), __int_as_float(pa.y), __int_as_float(pa.z), __int_as_float(pa.w)};
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
           const int64_t e = 4 * (int64_t)g + b;
           if (e >= lo_e && e < hi_e) {
-            const bool live = edge_live(d.w[b], pa[b]);
+            const bool live = edge_live(d.w[b], pb[b]);
             if (BWD) {
+              // an edge into S is never revealed (its target is not outside S)
               if (!in_seed_set(Q, va[b])) {
                 atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
-                if (live) {
-                  const int32_t v = va[b];
-                  const uint32_t bit = 1u << (v & 31);
-                  if (!(atomicOr(&bits[v >> 5], bit) & bit)) queue[atomicAdd(&s_tail, 1u)] = v;
-                }
+                if (live && claim(bits, va[b])) queue[atomicAdd(&s_tail, 1u)] = va[b];
               }
-            } else if (live && !in_seed_set(Q, va[b])) {
-              const int32_t v = va[b];
-              const uint32_t bit = 1u << (v & 31);
-              if (!(atomicOr(&bits[v >> 5], bit) & bit)) queue[atomicAdd(&s_tail, 1u)] = v;
+            } else if (live && claim(bits, va[b])) {
+              // S is marked in the bitmap, so a live edge into S claims nothing
+              queue[atomicAdd(&s_tail, 1u)] = va[b];
             }
           }
         }
@@ -1204,6 +1241,8 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       atomicAdd(&A.tier_sums[5], s_E);
     }
     for (uint32_t t = tid; t < Y; t += LB) bits[queue[t] >> 5] = 0u;
+    __syncthreads();
+    mark_seed_set(Q, bits, false, tid);
     __syncthreads();
   }
 }
@@ -1529,6 +1568,13 @@ hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t 
   else
     hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false>), dim3(blocks), dim3(256), 0, st, A);
   return hipGetLastError();
+}
+
+hipError_t large_occupancy(bool bwd, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      blocks_per_cu,
+      bwd ? reinterpret_cast<const void*>(&large_kernel<true>) : reinterpret_cast<const void*>(&large_kernel<false>),
+      LB, 0);
 }
 
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {

@@ -25,6 +25,7 @@ void small_variant_info(int v, int* k, int* hcap, int* rcap, int* r);
 hipError_t small_occupancy(int v, bool bwd, int* blocks_per_cu);
 hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
+hipError_t large_occupancy(bool bwd, int* blocks_per_cu);
 int tiny_cap();
 hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu);
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
@@ -248,10 +249,15 @@ oi_status ensure_large_pool(oi_graph* g) {
   const double per = (double)words * 4.0 + (double)g->n * 4.0;
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
-  double budget = std::min(16.0 * (1ull << 30), 0.25 * (double)freeb);
-  int blocks = (int)std::min<double>(1024.0, std::floor(budget / per));
+  // one workspace per resident block of the large kernel (forward and
+  // backward variants alike), within a quarter of free memory and 32 GiB
+  int occ_f = 0, occ_b = 0;
+  HIP_TRY(oi::large_occupancy(false, &occ_f));
+  HIP_TRY(oi::large_occupancy(true, &occ_b));
+  const int occ = std::max(1, std::max(occ_f, occ_b));
+  const double budget = std::min(32.0 * (1ull << 30), 0.25 * (double)freeb);
+  int blocks = (int)std::min<double>((double)occ * g->cus, std::floor(budget / per));
   if (blocks < 1) return fail(OI_ENOMEM, "no room for a large-cascade workspace");
-  blocks = std::min(blocks, 4 * g->cus);
   HIP_TRY(g->d_bits.ensure((size_t)blocks * (size_t)words * 4));
   HIP_TRY(g->d_queue.ensure((size_t)blocks * (size_t)g->n * 4));
   HIP_TRY(hipMemsetAsync(g->d_bits.p, 0, (size_t)blocks * (size_t)words * 4, g->stream));
@@ -294,7 +300,8 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   HIP_TRY(hipMemsetAsync(g->d_sums.p, 0, sums.size() * sizeof(unsigned long long), g->stream));
   HIP_TRY(hipMemsetAsync(g->d_ctl.p, 0, 16 * sizeof(unsigned long long), g->stream));
 
-  // control block: [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier sums
+  // control block: [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier sums,
+  // [11] counter2
   unsigned long long* ctl = g->d_ctl.as<unsigned long long>();
   oi::SampleLaunch A{};
   A.n = g->n;
@@ -311,6 +318,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   A.tier_sums = ctl + 5;
   A.counter = ctl;
   A.counter1 = ctl + 1;
+  A.counter2 = ctl + 11;
   A.list1 = g->d_def.as<unsigned long long>();
   A.nlist1 = reinterpret_cast<unsigned int*>(ctl + 2);
   A.list2 = g->d_def2.as<unsigned long long>();

@@ -71,6 +71,7 @@ struct SampleLaunch {
   unsigned long long* tier_sums;   // 2 per kernel (tiny, small, large): sum Y, sum E it finished
   unsigned long long* counter;     // flat work counter of the first kernel
   unsigned long long* counter1;    // work counter of the small kernel over list1
+  unsigned long long* counter2;    // work counter of the large kernel over list2
   unsigned long long* list1;       // flat indices handed from tiny to small
   unsigned int* nlist1;
   unsigned long long* list2;       // flat indices handed from small to large
