@@ -76,6 +76,8 @@ __device__ __forceinline__ const OI_CONST T* cptr(const T* p) {
 }
 
 typedef int v4i32 __attribute__((ext_vector_type(4)));
+// the same, for 16-byte loads at 8-byte aligned addresses (a row_ptr pair)
+typedef int v4i32_a8 __attribute__((ext_vector_type(4), aligned(8)));
 typedef unsigned long long v2u64 __attribute__((ext_vector_type(2)));
 
 __device__ __forceinline__ TabGroup load_tab(const TabGroup* base, int64_t g) {
@@ -288,6 +290,10 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   int64_t c_l = 0;
   const TabGroup* c_tab = nullptr;
   const int32_t* c_shash = nullptr;
+  // when the segment's Stage-1 table has a single entry, that entry v_0 and
+  // its row bounds: every sample of the segment starts by popping v_0
+  int32_t c_v0 = 0;
+  int64_t c_rb0 = 0, c_re0 = 0;
   bool exhausted = false;
   uint32_t acc_seg = 0xFFFFFFFFu;
   unsigned long long acc_y = 0, acc_e = 0;
@@ -353,6 +359,11 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
           c_smask = Qp->smask;
           c_shash = Qp->shash;
           c_tab = Qp->tab;
+          if (c_l == 1) {
+            c_v0 = cptr(c_tab)->v[0];
+            c_rb0 = cptr(A.row_ptr)[c_v0];
+            c_re0 = cptr(A.row_ptr)[c_v0 + 1];
+          }
         }
         const uint64_t lim = cend < cseg_end ? cend : cseg_end;
         const uint64_t room = lim - cur;
@@ -397,36 +408,44 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     hand_over(pass_on, f, A.list1, A.nlist1, lane);
     pass_on = false;
     // (3) one round of independent loads: popping lanes fetch the next
-    // node's row bounds, expanding lanes their group of four edges or table
-    // entries; then one Philox block per working lane
-    int32_t tv[4] = {0, 0, 0, 0};
-    float tp[4] = {0.f, 0.f, 0.f, 0.f};
-    uint64_t tt[4] = {0, 0, 0, 0};
-    int64_t peb = 0, pee = 0;
+    // node's row bounds (16 bytes), expanding lanes their group of four edges
+    // (32 bytes) or table entries (48 bytes).  Every lane issues the same
+    // three 16-byte loads from addresses chosen per state (lanes with
+    // nothing to read point at row_ptr[0..1]), with no branch between them,
+    // so the three kinds of load are in flight together instead of one after
+    // another; the Philox block below overlaps their latency.
+    const OI_GLOBAL char* la = (const OI_GLOBAL char*)gptr(A.row_ptr);
+    const OI_GLOBAL char* lb = la;
+    const OI_GLOBAL char* lc = la;
     if (st == T_POP) {
       const int32_t u = vis[64 * qh];
-      peb = A.row_ptr[u];
-      pee = A.row_ptr[u + 1];
+      la = (const OI_GLOBAL char*)(gptr(A.row_ptr) + u);
     } else if (st == T_EXPAND) {
-      const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
-      const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
-      tv[0] = vv.x; tv[1] = vv.y; tv[2] = vv.z; tv[3] = vv.w;
-      tp[0] = pp.x; tp[1] = pp.y; tp[2] = pp.z; tp[3] = pp.w;
+      la = (const OI_GLOBAL char*)(gptr(A.eg) + g);
+      lb = la + 16;
     } else if (st == T_STAGE1) {
-      const TabGroup T = load_tab(tab, g);
-#pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        tv[b] = T.v[b];
-        tt[b] = T.thr[b];
-      }
+      la = (const OI_GLOBAL char*)(gptr(tab) + g);
+      lb = la + 16;
+      lc = la + 32;
     }
+    const v4i32 ra = *(const OI_GLOBAL v4i32_a8*)la;
+    const v4i32 rb = *(const OI_GLOBAL v4i32*)lb;
+    const v4i32 rc = *(const OI_GLOBAL v4i32*)lc;
     Words d;
     d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0;
-    if (st == T_START || st == T_STAGE1 || st == T_EXPAND) {
+    if ((st == T_START && c_l > 1) || st == T_STAGE1 || st == T_EXPAND) {
       const uint32_t kind = st == T_START ? KIND_SELECT : (st == T_STAGE1 ? KIND_STAGE1 : KIND_EDGE);
       d = philox_draw(qid, A.seed, kind, stream, s, st == T_START ? 0ull : (uint64_t)g);
     }
     // (4) consume
+    const int32_t tv[4] = {ra.x, ra.y, ra.z, ra.w};
+    const float tp[4] = {__int_as_float(rb.x), __int_as_float(rb.y), __int_as_float(rb.z), __int_as_float(rb.w)};
+    const uint64_t tt[4] = {(uint64_t)(uint32_t)rb.x | ((uint64_t)(uint32_t)rb.y << 32),
+                            (uint64_t)(uint32_t)rb.z | ((uint64_t)(uint32_t)rb.w << 32),
+                            (uint64_t)(uint32_t)rc.x | ((uint64_t)(uint32_t)rc.y << 32),
+                            (uint64_t)(uint32_t)rc.z | ((uint64_t)(uint32_t)rc.w << 32)};
+    const int64_t peb = (int64_t)((uint64_t)(uint32_t)ra.x | ((uint64_t)(uint32_t)ra.y << 32));
+    const int64_t pee = (int64_t)((uint64_t)(uint32_t)ra.z | ((uint64_t)(uint32_t)ra.w << 32));
     if (st == T_POP) {
       ++qh;
       E += (unsigned long long)(pee - peb);
@@ -436,6 +455,25 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         g = (uint32_t)(peb >> 2);
         gend = (uint32_t)((pee + 3) >> 2);
         st = T_EXPAND;
+      }
+    } else if (st == T_START && c_l == 1) {
+      // Stage 1 with a single table entry (lines 2-3 of Alg. 1 select it
+      // whatever U is, and there is no further entry): v_0 is activated and,
+      // with the row bounds read once per segment, popped at once.  The
+      // lanes starting now all belong to the current segment.
+      vis[0] = c_v0;
+      cnt = 1;
+      qh = 1;
+      E = (unsigned long long)(c_re0 - c_rb0);
+      if (BWD) atomicAdd(&A.acc_tab[0], (unsigned long long)y);
+      if (c_re0 > c_rb0) {
+        lo_e = c_rb0;
+        hi_e = c_re0;
+        g = (uint32_t)(c_rb0 >> 2);
+        gend = (uint32_t)((c_re0 + 3) >> 2);
+        st = T_EXPAND;
+      } else {
+        st = T_POP;
       }
     } else if (st == T_START) {
       // Stage 1, lines 2-3 of Alg. 1 (a single entry is selected whatever U is)
