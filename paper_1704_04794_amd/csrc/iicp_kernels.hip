@@ -403,7 +403,28 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         y = A.y_in[oidx];
         pass_on |= y > (uint32_t)CAP;
       }
-      if (pass_on) st = T_IDLE;
+      if (pass_on) {
+        st = T_IDLE;
+      } else if (c_l == 1) {
+        // Stage 1 with a single table entry (lines 2-3 of Alg. 1 select it
+        // whatever U is, and no entry follows): v_0 is activated and, with
+        // its row bounds read once per segment, popped at once, so the
+        // sample examines its first edge group in this very iteration.
+        vis[0] = c_v0;
+        cnt = 1;
+        qh = 1;
+        E = (unsigned long long)(c_re0 - c_rb0);
+        if (BWD) atomicAdd(&A.acc_tab[0], (unsigned long long)y);
+        if (c_re0 > c_rb0) {
+          lo_e = c_rb0;
+          hi_e = c_re0;
+          g = (uint32_t)(c_rb0 >> 2);
+          gend = (uint32_t)((c_re0 + 3) >> 2);
+          st = T_EXPAND;
+        } else {
+          st = T_POP;
+        }
+      }
     }
     hand_over(pass_on, f, A.list1, A.nlist1, lane);
     pass_on = false;
@@ -417,7 +438,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     const OI_GLOBAL char* la = (const OI_GLOBAL char*)gptr(A.row_ptr);
     const OI_GLOBAL char* lb = la;
     const OI_GLOBAL char* lc = la;
-    if (st == T_POP) {
+    if (st == T_POP && qh < cnt) {
       const int32_t u = vis[64 * qh];
       la = (const OI_GLOBAL char*)(gptr(A.row_ptr) + u);
     } else if (st == T_EXPAND) {
@@ -433,7 +454,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     const v4i32 rc = *(const OI_GLOBAL v4i32*)lc;
     Words d;
     d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0;
-    if ((st == T_START && c_l > 1) || st == T_STAGE1 || st == T_EXPAND) {
+    if (st == T_START || st == T_STAGE1 || st == T_EXPAND) {
       const uint32_t kind = st == T_START ? KIND_SELECT : (st == T_STAGE1 ? KIND_STAGE1 : KIND_EDGE);
       d = philox_draw(qid, A.seed, kind, stream, s, st == T_START ? 0ull : (uint64_t)g);
     }
@@ -447,33 +468,19 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     const int64_t peb = (int64_t)((uint64_t)(uint32_t)ra.x | ((uint64_t)(uint32_t)ra.y << 32));
     const int64_t pee = (int64_t)((uint64_t)(uint32_t)ra.z | ((uint64_t)(uint32_t)ra.w << 32));
     if (st == T_POP) {
-      ++qh;
-      E += (unsigned long long)(pee - peb);
-      if (pee > peb) {
-        lo_e = peb;
-        hi_e = pee;
-        g = (uint32_t)(peb >> 2);
-        gend = (uint32_t)((pee + 3) >> 2);
-        st = T_EXPAND;
-      }
-    } else if (st == T_START && c_l == 1) {
-      // Stage 1 with a single table entry (lines 2-3 of Alg. 1 select it
-      // whatever U is, and there is no further entry): v_0 is activated and,
-      // with the row bounds read once per segment, popped at once.  The
-      // lanes starting now all belong to the current segment.
-      vis[0] = c_v0;
-      cnt = 1;
-      qh = 1;
-      E = (unsigned long long)(c_re0 - c_rb0);
-      if (BWD) atomicAdd(&A.acc_tab[0], (unsigned long long)y);
-      if (c_re0 > c_rb0) {
-        lo_e = c_rb0;
-        hi_e = c_re0;
-        g = (uint32_t)(c_rb0 >> 2);
-        gend = (uint32_t)((c_re0 + 3) >> 2);
-        st = T_EXPAND;
-      } else {
-        st = T_POP;
+      // a lane that entered T_POP with its queue drained during this
+      // iteration (a single-entry start whose node has no out-edges) read
+      // nothing; the next iteration finishes it
+      if (qh < cnt) {
+        ++qh;
+        E += (unsigned long long)(pee - peb);
+        if (pee > peb) {
+          lo_e = peb;
+          hi_e = pee;
+          g = (uint32_t)(peb >> 2);
+          gend = (uint32_t)((pee + 3) >> 2);
+          st = T_EXPAND;
+        }
       }
     } else if (st == T_START) {
       // Stage 1, lines 2-3 of Alg. 1 (a single entry is selected whatever U is)
@@ -727,6 +734,18 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
   const bool from_list = A.small_from_list1 != 0;
   const uint64_t total = from_list ? (uint64_t)*A.nlist1 : A.total;
   unsigned long long* const counter = from_list ? A.counter1 : A.counter;
+  if (from_list && total <= A.small_direct_max) {
+    // Few samples were handed over: one block per sample in the large
+    // kernel finishes them sooner than a wave working through its slots, so
+    // block 0 forwards the list unchanged and every block leaves.
+    __shared__ unsigned int s_base;
+    if (blockIdx.x == 0) {
+      if (threadIdx.x == 0 && total) s_base = atomicAdd(A.nlist2, (unsigned int)total);
+      __syncthreads();
+      for (uint32_t t = threadIdx.x; t < (uint32_t)total; t += blockDim.x) A.list2[s_base + t] = A.list1[t];
+    }
+    return;
+  }
 
   while (true) {
     // ---- refill free slots from the work counter ----------------------
@@ -1358,11 +1377,21 @@ __global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const P
       continue;
     }
     unsigned long long lo = 0, hi = 0;
-    for (uint64_t i = lo_pair + threadIdx.x; i < hi_pair; i += 256) {
-      const uint64_t p = P.out_off + 2 * (i - P.flat0);
-      const uint2 v = *reinterpret_cast<const uint2*>(&y[p]);
-      const unsigned long long d = v.x > v.y ? (unsigned long long)(v.x - v.y) : (unsigned long long)(v.y - v.x);
-      add128(lo, hi, d * d, 0);
+    // four independent loads in flight per thread
+    for (uint64_t i = lo_pair + threadIdx.x; i < hi_pair; i += 4 * 256) {
+      uint2 v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const uint64_t ii = i + (uint64_t)u * 256;
+        v[u] = make_uint2(0u, 0u);
+        if (ii < hi_pair) v[u] = *reinterpret_cast<const uint2*>(&y[P.out_off + 2 * (ii - P.flat0)]);
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const unsigned long long d =
+            v[u].x > v[u].y ? (unsigned long long)(v[u].x - v[u].y) : (unsigned long long)(v[u].y - v[u].x);
+        add128(lo, hi, d * d, 0);
+      }
     }
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) {

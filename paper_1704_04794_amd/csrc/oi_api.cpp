@@ -324,6 +324,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   A.list2 = g->d_def2.as<unsigned long long>();
   A.nlist2 = reinterpret_cast<unsigned int*>(ctl + 3);
   A.small_from_list1 = g->use_tiny ? 1 : 0;
+  A.small_direct_max = (uint32_t)g->large_blocks;
   A.err = reinterpret_cast<unsigned int*>(ctl + 4);
   A.chunk = g->chunk;
   A.tiny_chunk = g->tiny_chunk;

@@ -77,6 +77,7 @@ struct SampleLaunch {
   unsigned long long* list2;       // flat indices handed from small to large
   unsigned int* nlist2;
   int32_t small_from_list1;        // 1 if the tiny kernel ran before the small one
+  uint32_t small_direct_max;       // at most this many handed samples go straight to the large kernel
   unsigned int* err;               // nonzero on an internal inconsistency
   uint32_t chunk;                  // samples the small kernel takes per counter increment
   uint32_t tiny_chunk;             // samples the tiny kernel takes per counter increment

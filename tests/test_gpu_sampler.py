@@ -185,3 +185,24 @@ def test_degenerate_inputs(P):
     H = _gpu_graph(P, h)
     assert H.sample_fixed([0], 10)[2]["beta0"] == 0.0
     H.close()
+
+
+def test_few_handed_samples_go_straight_to_the_large_kernel(P):
+    """A 40-leaf star at p = 0.2 from the centre: only the rare samples with
+    more than 16 activated leaves leave the tiny kernel, few enough that the
+    small kernel forwards them to the large kernel unprocessed.  Y and E stay
+    bit-exact, and so does the backward's use of the same path."""
+    import torch
+    g = star_graph(np.full(40, 0.2, np.float32))
+    G = _gpu_graph(P, g)
+    G.timing(True)
+    _compare(P, g, [0], 20000, G=G, label="star40 few hand-overs")
+    t = G.timing()
+    assert 0 < t["handed_small"] <= 512 and t["small_y"] == 0 and t["large_y"] > 0, t
+    grad = torch.empty(g.m, dtype=torch.float32, device="cuda")
+    G.backward([0], 20000, grad)
+    o = O.backward(g, [0], 0, RUN_SEED, 0, 20000)
+    ref = o["beta0"] * o["acc"] / 20000
+    got = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    G.close()
