@@ -1106,14 +1106,15 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
 // large_kernel: one block per handed-over sample, global bitmap + queue
 // ---------------------------------------------------------------------------
 // A block of LB threads runs one sample at a time, taking samples from a
-// work counter.  The visited set is a bitmap of n bits and the queue an array
+// work counter; as many blocks run as fit on the GPU (within the workspace
+// budget), so many samples are in flight at once.  The visited set is a bitmap of n bits and the queue an array
 // of n node ids, both owned by the block; the seed set is marked in the
 // bitmap while the sample runs, so an edge into S is never pushed.  Stage 2
 // expands the queue in batches of up to LB nodes: each thread reads one
 // node's row bounds, a block scan lays the batch's edge groups out in one
 // index space, and thread t takes groups t, t + LB, ... of it.  After the
 // sample the bits it set (the queue and S) are cleared again.
-constexpr int LB = 1024;
+constexpr int LB = 256;
 
 __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, int tid, uint32_t* total) {
   const int lane = tid & 63, wid = tid >> 6;
