@@ -83,7 +83,8 @@ typedef struct {
  * probabilities in [0, 1], Sec. 2.1: edge (u, v) is live with probability
  * w(u, v)).  Edge ids are CSR positions.  If device_ptrs is nonzero the three
  * arrays are device pointers, else host pointers.  hip_stream is a
- * hipStream_t (NULL = default stream).  Limits: n < 2^31, out-degree < 2^29.
+ * hipStream_t (NULL = default stream).  Limits: n < 2^31, m <= 2^32 - 16,
+ * out-degree < 2^29.
  * Errors: OI_EINVAL for malformed CSR or p outside [0, 1] (NaN included).
  */
 oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const int32_t* col, const float* p,

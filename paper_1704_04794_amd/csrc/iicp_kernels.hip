@@ -276,7 +276,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   const TabGroup* tab = nullptr;
   const int32_t* shash = nullptr;
   unsigned long long E = 0;
-  int64_t lo_e = 0, hi_e = 0;
+  uint32_t lo_e = 0, hi_e = 0;  // edge ids (m < 2^32) or Stage-1 entry indices
   // the wave's current work chunk [cur, cend) and the segment of cur
   // (wave-uniform); every refill hands out samples of one segment only, so
   // the segment and its query are read with scalar loads, once per refill
@@ -416,8 +416,8 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         E = (unsigned long long)(c_re0 - c_rb0);
         if (BWD) atomicAdd(&A.acc_tab[0], (unsigned long long)y);
         if (c_re0 > c_rb0) {
-          lo_e = c_rb0;
-          hi_e = c_re0;
+          lo_e = (uint32_t)c_rb0;
+          hi_e = (uint32_t)c_re0;
           g = (uint32_t)(c_rb0 >> 2);
           gend = (uint32_t)((c_re0 + 3) >> 2);
           st = T_EXPAND;
@@ -475,8 +475,8 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         ++qh;
         E += (unsigned long long)(pee - peb);
         if (pee > peb) {
-          lo_e = peb;
-          hi_e = pee;
+          lo_e = (uint32_t)peb;
+          hi_e = (uint32_t)pee;
           g = (uint32_t)(peb >> 2);
           gend = (uint32_t)((pee + 3) >> 2);
           st = T_EXPAND;
@@ -520,8 +520,8 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       E = (unsigned long long)(ql - 1 - i);
       if (BWD) atomicAdd(&A.acc_tab[i], (unsigned long long)y);
       if (i + 1 < ql) {
-        lo_e = i + 1;
-        hi_e = ql;
+        lo_e = (uint32_t)(i + 1);
+        hi_e = (uint32_t)ql;
         g = (uint32_t)((i + 1) >> 2);
         gend = (uint32_t)((ql + 3) >> 2);
         st = T_STAGE1;
@@ -533,7 +533,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       uint32_t live = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
-        const int64_t x = 4 * (int64_t)g + b;
+        const uint32_t x = 4 * g + b;
         if (x >= lo_e && x < hi_e) {
           if (st == T_STAGE1) {
             if ((uint64_t)d.w[b] < tt[b]) {

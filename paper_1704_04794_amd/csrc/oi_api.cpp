@@ -811,7 +811,8 @@ oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const in
                           int device_ptrs, void* hip_stream, oi_graph** out) {
   if (!out) return fail(OI_EINVAL, "out is null");
   *out = nullptr;
-  if (n <= 0 || n >= (1ll << 31) || m < 0) return fail(OI_EINVAL, "need 0 < n < 2^31 and m >= 0");
+  if (n <= 0 || n >= (1ll << 31) || m < 0 || m > (int64_t)0xFFFFFFF0ll)
+    return fail(OI_EINVAL, "need 0 < n < 2^31 and 0 <= m <= 2^32 - 16");
   if (!row_ptr || (m > 0 && (!col || !p))) return fail(OI_EINVAL, "null CSR array");
   std::unique_ptr<oi_graph> g(new oi_graph());
   g->n = n;

@@ -52,6 +52,9 @@ def test_malformed_graphs_are_rejected_on_the_host():
         (3, np.array([1, 1, 2, 2], np.int64), col, p),   # row_ptr[0] != 0
         (0, np.array([0], np.int64), col[:0], p[:0]),    # n = 0
     ]
+    with pytest.raises(P.OiError) as ei:                 # more edges than 32-bit edge ids allow
+        P.oi_graph_create(3, 1 << 32, rp, col, p)
+    assert ei.value.status == P._binding.OI_EINVAL
     for n, r, c, q in bad:
         with pytest.raises(P.OiError) as ei:
             P.oi_graph_create(n, c.size, r, c, q)
