@@ -37,8 +37,8 @@ BYTES_PER_EDGE = 8   # col (int32) + p (fp32) per examined edge
 # rocprofv3 counter passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the scales a
 # 1 GiB device copy gives those counters), mean over the 83 launches of one
 # estimate.  Reported only while the kernel sources hash to what was measured.
-TRAFFIC = {"sources_sha1": "9144a49f5e6fad61ba0bd070cf42e3c52b3d511d", "kernel": "tiny_kernel",
-           "bytes_per_launch": 263130521.6}
+TRAFFIC = {"sources_sha1": "9da15dee02b00053a977eefb6e2d4c2ec3112153", "kernel": "tiny_kernel",
+           "bytes_per_launch": 270563635.2, "l2_hit_rate": 0.778}
 KERNEL_SOURCES = ("paper_1704_04794_amd/csrc/iicp_kernels.hip", "paper_1704_04794_amd/csrc/oi_device.hpp")
 
 
@@ -256,6 +256,7 @@ def main():
         "oi": res["oi"] if res else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{kern}_kernel"),
+                     "l2_hit_rate": TRAFFIC["l2_hit_rate"] if measured_traffic(f"{kern}_kernel") else None,
                      "kernel": f"{kern}_kernel", "avg_launch_ms": avg_ms, "launches": tm["launches"],
                      "bytes_per_launch": kbytes / launches},
         "sampler": {k: tm[k] for k in ("tiny_ms", "small_ms", "large_ms", "samples", "handed_small",
