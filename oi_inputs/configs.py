@@ -19,6 +19,8 @@ The Philox run seed used by tests and the bench is RUN_SEED.
 """
 from __future__ import annotations
 
+import os
+
 import numpy as np
 
 from . import graphs as G
@@ -49,12 +51,13 @@ def _probs(g, model, number):
     raise ValueError(model)
 
 
-def make_config(name: str, n: int | None = None, m: int | None = None):
+def make_config(name: str, n: int | None = None, m: int | None = None, progress=None):
     """Build (graph, seed_sets, extra) for a workload.  `n`/`m` override the
     size (for scaled-down parity cases with the same recipe).
 
     seed_sets is a list of int32 arrays.  extra holds theta where relevant and
-    the eps/delta/sample counts of the workload."""
+    the eps/delta/sample counts of the workload.  `progress(done, total)` is
+    passed to the graph generator (called once per block of sources)."""
     c = dict(CONFIGS[name])
     num = c["number"]
     nn = c["n"] if n is None else n
@@ -63,7 +66,9 @@ def make_config(name: str, n: int | None = None, m: int | None = None):
     if name == "er2k":
         g = G.er_graph(nn, mm, num)
     else:
-        g = G.chung_lu_graph(nn, mm, c["gamma"], num)
+        # blocks generated in parallel for large graphs (same output)
+        workers = min(16, os.cpu_count() or 1) if nn >= (1 << 22) else 1
+        g = G.chung_lu_graph(nn, mm, c["gamma"], num, workers=workers, progress=progress)
     p, theta = _probs(g, c["model"], num)
     g = g.with_p(p)
     extra["theta"] = theta

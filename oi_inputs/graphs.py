@@ -122,8 +122,30 @@ def chung_lu_weights(n: int, m_target: float, gamma: float) -> np.ndarray:
     return w
 
 
+# Per-process state of the block generator (set before worker processes are
+# forked, so the large arrays are shared copy-on-write rather than pickled).
+_CL_STATE: dict = {}
+
+
+def _chung_lu_block(b0: int):
+    n, block, seed = _CL_STATE["n"], _CL_STATE["block"], _CL_STATE["seed"]
+    w_out, cdf = _CL_STATE["w_out"], _CL_STATE["cdf"]
+    b1 = min(n, b0 + block)
+    rng = np.random.Generator(np.random.PCG64([seed, b0 // block]))
+    d = rng.poisson(w_out[b0:b1])
+    tot = int(d.sum())
+    u = rng.random(tot)
+    tgt = np.searchsorted(cdf, u, side="right").astype(np.int64)
+    np.minimum(tgt, n - 1, out=tgt)
+    src = np.repeat(np.arange(b0, b1, dtype=np.int64), d)
+    keep = tgt != src
+    key = np.unique(src[keep] * n + tgt[keep])
+    s = key // n
+    return (key % n).astype(np.int32), np.bincount(s - b0, minlength=b1 - b0)
+
+
 def chung_lu_graph(n: int, m_target: float, gamma: float, seed: int,
-                   block: int = 1 << 20) -> Graph:
+                   block: int = 1 << 20, workers: int = 1, progress=None) -> Graph:
     """Directed Chung-Lu graph.
 
     Out- and in-weights use the same capped power-law sequence, each assigned
@@ -131,31 +153,39 @@ def chung_lu_graph(n: int, m_target: float, gamma: float, seed: int,
     are independent).  Source u draws d_u ~ Poisson(w_out[u]) targets i.i.d.
     from the in-weight distribution; self-loops and duplicates are dropped.
     Sources are generated in blocks of `block` nodes, each block with its own
-    PCG64 stream keyed by (seed, block index), so memory stays bounded.
+    PCG64 stream keyed by (seed, block index), so memory stays bounded and
+    `workers` processes can generate blocks in parallel with the same result.
+    `progress(done, total)` is called after each block if given.
     """
     top = np.random.Generator(np.random.PCG64(seed))
     w = chung_lu_weights(n, m_target, gamma)
     w_out = w[top.permutation(n)]
     w_in = w[top.permutation(n)]
+    del w
     cdf = np.cumsum(w_in)
+    del w_in
     cdf /= cdf[-1]
-    cols = []
-    degs = np.zeros(n, dtype=np.int64)
-    for b0 in range(0, n, block):
-        b1 = min(n, b0 + block)
-        rng = np.random.Generator(np.random.PCG64([seed, b0 // block]))
-        d = rng.poisson(w_out[b0:b1])
-        tot = int(d.sum())
-        u = rng.random(tot)
-        tgt = np.searchsorted(cdf, u, side="right").astype(np.int64)
-        np.minimum(tgt, n - 1, out=tgt)
-        src = np.repeat(np.arange(b0, b1, dtype=np.int64), d)
-        keep = tgt != src
-        key = np.unique(src[keep] * n + tgt[keep])
-        s = key // n
-        cols.append((key % n).astype(np.int32))
-        degs[b0:b1] = np.bincount(s - b0, minlength=b1 - b0)
-    col = np.concatenate(cols) if cols else np.zeros(0, dtype=np.int32)
+    _CL_STATE.update(n=n, block=block, seed=seed, w_out=w_out, cdf=cdf)
+    starts = list(range(0, n, block))
+    try:
+        parts = []
+        if workers > 1 and len(starts) > 1:
+            import multiprocessing as mp
+            with mp.get_context("fork").Pool(min(workers, len(starts))) as pool:
+                for part in pool.imap(_chung_lu_block, starts, chunksize=1):
+                    parts.append(part)
+                    if progress:
+                        progress(len(parts), len(starts))
+        else:
+            for b0 in starts:
+                parts.append(_chung_lu_block(b0))
+                if progress:
+                    progress(len(parts), len(starts))
+    finally:
+        _CL_STATE.clear()
+    degs = np.concatenate([d for _, d in parts]) if parts else np.zeros(0, dtype=np.int64)
+    col = np.concatenate([c for c, _ in parts]) if parts else np.zeros(0, dtype=np.int32)
+    del parts
     row_ptr = np.zeros(n + 1, dtype=np.int64)
     np.cumsum(degs, out=row_ptr[1:])
     g = Graph(int(n), row_ptr, col, np.zeros(col.size, dtype=np.float32))

@@ -1110,11 +1110,12 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
 // budget), so many samples are in flight at once.  The visited set is a bitmap of n bits and the queue an array
 // of n node ids, both owned by the block; the seed set is marked in the
 // bitmap while the sample runs, so an edge into S is never pushed.  Stage 2
-// expands the queue in batches of up to LB nodes: each thread reads one
-// node's row bounds, a block scan lays the batch's edge groups out in one
+// expands the queue in batches of up to LB * LBN nodes: each thread reads
+// LBN nodes' row bounds, a block scan lays the batch's edge groups out in one
 // index space, and thread t takes groups t, t + LB, ... of it.  After the
 // sample the bits it set (the queue and S) are cleared again.
 constexpr int LB = 256;
+constexpr int LBN = 4;  // queued nodes per thread per expansion batch
 
 __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, int tid, uint32_t* total) {
   const int lane = tid & 63, wid = tid >> 6;
@@ -1166,10 +1167,9 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_tail;
   __shared__ unsigned long long s_E;
   __shared__ uint32_t wtot[LB / 64];
-  __shared__ uint32_t it_scan[LB];
-  __shared__ int64_t it_eb[LB];
-  __shared__ int64_t it_ee[LB];
-  __shared__ uint32_t it_g0[LB];
+  __shared__ uint32_t it_scan[LB * LBN];
+  __shared__ uint32_t it_eb[LB * LBN];
+  __shared__ uint32_t it_ee[LB * LBN];
   __shared__ int64_t s_i;
   __shared__ uint32_t s_di;
   const int tid = threadIdx.x;
@@ -1221,34 +1221,47 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       }
     }
     __syncthreads();
-    // Stage 2, lines 7-12: expand the queue in batches of LB nodes
+    // Stage 2, lines 7-12: expand the queue in batches of up to LB * LBN
+    // nodes, LBN consecutive queue entries per thread (their row reads are
+    // independent, so they are in flight together)
     uint32_t head = 0;
     while (true) {
       const uint32_t tail = s_tail;
       __syncthreads();
       if (head >= tail) break;
-      const uint32_t nb = tail - head < (uint32_t)LB ? tail - head : (uint32_t)LB;
-      uint32_t ntask = 0, g0 = 0;
-      int64_t eb = 0, ee = 0;
-      if ((uint32_t)tid < nb) {
-        const int32_t u = queue[head + tid];
-        eb = A.row_ptr[u];
-        ee = A.row_ptr[u + 1];
-        if (ee > eb) {
-          g0 = (uint32_t)(eb >> 2);
-          ntask = (uint32_t)((ee + 3) >> 2) - g0;
-          atomicAdd(&s_E, (unsigned long long)(ee - eb));
+      const uint32_t nb = tail - head < (uint32_t)(LB * LBN) ? tail - head : (uint32_t)(LB * LBN);
+      uint32_t rb[LBN], re[LBN], part[LBN];
+      uint32_t mine = 0;
+      unsigned long long eloc = 0;
+#pragma unroll
+      for (int k = 0; k < LBN; ++k) {
+        const uint32_t j = (uint32_t)(LBN * tid + k);
+        rb[k] = re[k] = 0;
+        if (j < nb) {
+          const int32_t u = queue[head + j];
+          rb[k] = (uint32_t)A.row_ptr[u];
+          re[k] = (uint32_t)A.row_ptr[u + 1];
         }
       }
+#pragma unroll
+      for (int k = 0; k < LBN; ++k) {
+        eloc += re[k] - rb[k];
+        mine += re[k] > rb[k] ? ((re[k] + 3) >> 2) - (rb[k] >> 2) : 0u;
+        part[k] = mine;  // inclusive over this thread's entries
+      }
+      if (eloc) atomicAdd(&s_E, eloc);
       uint32_t total;
-      const uint32_t sc = block_incl_scan(ntask, wtot, tid, &total);
-      it_scan[tid] = sc;
-      it_eb[tid] = eb;
-      it_ee[tid] = ee;
-      it_g0[tid] = g0;
+      const uint32_t base = block_incl_scan(mine, wtot, tid, &total) - mine;
+#pragma unroll
+      for (int k = 0; k < LBN; ++k) {
+        const uint32_t j = (uint32_t)(LBN * tid + k);
+        it_scan[j] = base + part[k];
+        it_eb[j] = rb[k];
+        it_ee[j] = re[k];
+      }
       __syncthreads();
       for (uint32_t t = tid; t < total; t += LB) {
-        int lo = 0, hi = (int)nb - 1;
+        int lo = 0, hi = (int)nb - 1;  // first entry whose groups end after t
         while (lo < hi) {
           const int mid = (lo + hi) >> 1;
           if (it_scan[mid] > t)
@@ -1256,9 +1269,9 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
           else
             lo = mid + 1;
         }
-        const uint32_t base = lo ? it_scan[lo - 1] : 0u;
-        const uint32_t g = it_g0[lo] + (t - base);
-        const int64_t lo_e = it_eb[lo], hi_e = it_ee[lo];
+        const uint32_t before = lo ? it_scan[lo - 1] : 0u;
+        const uint32_t lo_e = it_eb[lo], hi_e = it_ee[lo];
+        const uint32_t g = (lo_e >> 2) + (t - before);
         const Words d = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, g);
         const OI_GLOBAL char* q = (const OI_GLOBAL char*)(gptr(A.eg) + g);
         const v4i32 va = *(const OI_GLOBAL v4i32*)q;
@@ -1266,7 +1279,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         const float pb[4] = {__int_as_float(pa.x), __int_as_float(pa.y), __int_as_float(pa.z), __int_as_float(pa.w)};
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
-          const int64_t e = 4 * (int64_t)g + b;
+          const uint32_t e = 4 * g + b;
           if (e >= lo_e && e < hi_e) {
             const bool live = edge_live(d.w[b], pb[b]);
             if (BWD) {
