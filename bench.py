@@ -117,6 +117,81 @@ def backward_ratio(P, N=1_000_000, reps=5):
             "note": "wall time per call incl. host work, best of %d; backward reuses the forward's Y" % reps}
 
 
+def billion_edge(P, args):
+    """The 1e8-node / 1.5e9-edge weighted-cascade workload: build and upload
+    time, the random-gather probe, fixed-count IICP throughput for one seed
+    set of each size (1, 10, 100), one full eps = 0.05 SOIEA estimate of the
+    |S| = 1 set, one backward dOI/dp over all edges for the |S| = 100 set, and
+    the CPU oracle on the |S| = 1 set."""
+    import torch
+
+    from oi_inputs import make_config
+    t0 = time.perf_counter()
+
+    def progress(done, total):
+        if done % 16 == 0 or done == total:
+            log(f"generated {done}/{total} blocks of sources ({time.perf_counter() - t0:.0f}s)")
+
+    g, sets, extra = make_config("cl100m", progress=progress)
+    build_s = time.perf_counter() - t0
+    log(f"cl100m n={g.n} m={g.m} built in {build_s:.1f}s")
+    t = time.perf_counter()
+    G = P.Graph.from_inputs(g)
+    torch.cuda.synchronize()
+    upload_s = time.perf_counter() - t
+    probe = gather_roofline(G)
+    out = {"metric": "IICP samples/s and GTEPS per seed-set size; eps=0.05 estimate; backward over all edges",
+           "workload": f"cl100m: Chung-Lu n=1e8 m={g.m} gamma=2.1 WC p, seed sets of the 256-set list "
+                       "(|S| = 1, 10, 100: sets 0, 1, 2)",
+           "build_s": build_s, "upload_s": upload_s, "gather_probe_gbps": probe["gbps"], "fixed": []}
+    for qi, N in ((0, 1 << 26), (1, 1 << 20), (2, 1 << 15)):
+        S = sets[qi]
+        G.sample_fixed(S, 4096, query_id=qi)
+        G.timing(True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        y, _, r = G.sample_fixed(S, N, query_id=qi)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        tm = G.timing()
+        row = {"k": int(len(S)), "query": qi, "samples": N, "seconds": dt, "samples_per_s": N / dt,
+               "gteps": r["edges_examined"] / dt / 1e9, "y_mean": r["sum_y"] / N, "beta0": r["beta0"],
+               "kernel_ms": {k: tm[f"{k}_ms"] for k in ("tiny", "small", "large")}}
+        out["fixed"].append(row)
+        log(f"fixed |S|={len(S)}: {row}")
+    S = sets[0]
+    t = time.perf_counter()
+    r = G.estimate(S, extra["eps"], extra["delta"], query_id=0)
+    dt = time.perf_counter() - t
+    out["estimate"] = {"k": int(len(S)), "eps": extra["eps"], "delta": extra["delta"], "seconds": dt,
+                       "samples": r["samples_x"] + r["samples_xp"], "oi": r["oi"], "is": r["is_"],
+                       "rounds": r["rounds"], "samples_per_s": (r["samples_x"] + r["samples_xp"]) / dt}
+    log(f"estimate: {out['estimate']}")
+    S = sets[2]
+    N = 1 << 14
+    grad = torch.empty(g.m, dtype=torch.float32, device="cuda")
+    y, _, _ = G.sample_fixed(S, N, query_id=2)
+    G.backward(S, N, grad, y_in=y, query_id=2)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    y, _, _ = G.sample_fixed(S, N, query_id=2)
+    torch.cuda.synchronize()
+    tf = time.perf_counter() - t
+    t = time.perf_counter()
+    G.backward(S, N, grad, y_in=y, query_id=2)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t
+    out["backward"] = {"k": int(len(S)), "samples": N, "edges": g.m, "forward_ms": tf * 1e3,
+                       "backward_ms": tb * 1e3, "ratio": tb / tf,
+                       "nonzero_grad_edges": int((grad != 0).sum().item())}
+    log(f"backward: {out['backward']}")
+    del grad
+    G.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(g, sets[0], args.cpu_seconds)
+    return out
+
+
 def batched_vs_single(P, args):
     """Seed-set estimates/s on the 4M-node weighted-cascade workload: a seeded
     stratified subset of its 4,096 seed sets (equal numbers from the uniform
@@ -168,8 +243,9 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the backward/forward ratio")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--variant", type=int, default=-1)
-    ap.add_argument("--workload", choices=("cl1m", "cl4m"), default="cl1m",
-                    help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time")
+    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m"), default="cl1m",
+                    help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time; "
+                         "cl100m: the billion-edge graph")
     ap.add_argument("--queries", type=int, default=32, help="cl4m: number of seed sets in the subset")
     ap.add_argument("--eps", type=float, default=-1.0, help="cl4m: eps (default: the workload's 0.1)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -192,6 +268,9 @@ def main():
     torch.cuda.set_device(0)
     if args.workload == "cl4m":
         print(json.dumps(batched_vs_single(P, args)), flush=True)
+        return
+    if args.workload == "cl100m":
+        print(json.dumps(billion_edge(P, args)), flush=True)
         return
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")

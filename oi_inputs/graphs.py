@@ -135,7 +135,11 @@ def _chung_lu_block(b0: int):
     d = rng.poisson(w_out[b0:b1])
     tot = int(d.sum())
     u = rng.random(tot)
-    tgt = np.searchsorted(cdf, u, side="right").astype(np.int64)
+    # the same searchsorted, evaluated in sorted order of u (cache friendly)
+    order = np.argsort(u)
+    tgt = np.empty(tot, dtype=np.int64)
+    tgt[order] = np.searchsorted(cdf, u[order], side="right")
+    del order
     np.minimum(tgt, n - 1, out=tgt)
     src = np.repeat(np.arange(b0, b1, dtype=np.int64), d)
     keep = tgt != src
