@@ -192,6 +192,16 @@ oi_status oi_timing_get(oi_graph* g, oi_timing* out);
  * zero) values keep the current setting.  Results do not depend on any of
  * these. */
 oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_chunk, int64_t round_max);
+/* Routing of large samples.  small_direct: 0 (default) lets the small
+ * kernel forward the samples the tiny kernel hands over straight to the
+ * large kernel when there are no more of them than large-kernel blocks; 1
+ * always forwards them (the small kernel does no sampling); 2 never does;
+ * -1 keeps the setting.  large_qcap > 0 sets the queue entries per block of
+ * the large kernel's main pool (default min(n, 2^20)); a sample that
+ * activates more nodes is finished by a second pass with n-entry queues.
+ * Changing large_qcap reallocates the pool.  Results do not depend on
+ * either setting.  Errors: OI_EINVAL for a null graph or small_direct > 2. */
+oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
 int oi_num_variants(void);
 oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* ring_cap, int* rounds_per_pass);
 

@@ -83,6 +83,7 @@ def _load():
         "oi_set_tuning": [vp, ci, ci, ci, ci, i64],
         "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
         "oi_gather_probe": [vp, u64, u32, P(u64), P(u64), P(dbl)],
+        "oi_set_routing": [vp, ci, i64],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -236,6 +237,10 @@ def oi_timing_get(g):
 def oi_set_tuning(g, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1):
     _check("oi_set_tuning", _lib.oi_set_tuning(g, int(variant), int(chunk), int(tiny), int(tiny_chunk),
                                                 int(round_max)))
+
+
+def oi_set_routing(g, small_direct=-1, large_qcap=-1):
+    _check("oi_set_routing", _lib.oi_set_routing(g, int(small_direct), int(large_qcap)))
 
 
 def oi_num_variants():

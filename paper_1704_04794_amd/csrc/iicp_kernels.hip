@@ -1162,6 +1162,14 @@ __device__ __forceinline__ bool claim(uint32_t* bits, int32_t v) {
   return !(atomicOr(&bits[v >> 5], bit) & bit);
 }
 
+// Appends v to a block's queue of capacity qcap.  The tail keeps counting
+// past the capacity, which is how the block notices that the sample has
+// outgrown its queue.
+__device__ __forceinline__ void push(int32_t* queue, uint32_t* tail, uint32_t qcap, int32_t v) {
+  const uint32_t pos = atomicAdd(tail, 1u);
+  if (pos < qcap) queue[pos] = v;
+}
+
 template <bool BWD>
 __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_tail;
@@ -1174,7 +1182,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_di;
   const int tid = threadIdx.x;
   uint32_t* bits = A.bits + (int64_t)blockIdx.x * A.bits_words;
-  int32_t* queue = A.queue + (int64_t)blockIdx.x * A.n;
+  int32_t* queue = A.queue + (int64_t)blockIdx.x * A.queue_stride;
   const uint32_t nd = *A.nlist2;
   while (true) {
     if (tid == 0) s_di = (uint32_t)atomicAdd(A.counter2, 1ull);
@@ -1188,6 +1196,18 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
     const uint64_t s = S.first + (f - S.flat0);
     const uint64_t oidx = S.out_off + (f - S.flat0);
     const unsigned long long y = BWD ? A.y_in[oidx] : 0ull;
+    if (BWD && y > A.qcap) {
+      // known too large for this pass's queues (the backward must not start
+      // a sample it cannot finish: its accumulations cannot be undone)
+      if (tid == 0) {
+        if (A.list3)
+          A.list3[atomicAdd(A.nlist3, 1u)] = f;
+        else
+          atomicOr(A.err, 16u);
+      }
+      __syncthreads();
+      continue;
+    }
     mark_seed_set(Q, bits, true, tid);
     __syncthreads();
     if (tid == 0) {
@@ -1216,7 +1236,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         const int64_t j = 4 * g + b;
         if (j > i && j < Q.l && (uint64_t)d.w[b] < T.thr[b]) {
           if (BWD) atomicAdd(&A.acc_tab[j], y);
-          if (claim(bits, T.v[b])) queue[atomicAdd(&s_tail, 1u)] = T.v[b];
+          if (claim(bits, T.v[b])) push(queue, &s_tail, A.qcap, T.v[b]);
         }
       }
     }
@@ -1228,7 +1248,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
     while (true) {
       const uint32_t tail = s_tail;
       __syncthreads();
-      if (head >= tail) break;
+      if (head >= tail || tail > A.qcap) break;
       const uint32_t nb = tail - head < (uint32_t)(LB * LBN) ? tail - head : (uint32_t)(LB * LBN);
       uint32_t rb[LBN], re[LBN], part[LBN];
       uint32_t mine = 0;
@@ -1286,11 +1306,11 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
               // an edge into S is never revealed (its target is not outside S)
               if (!in_seed_set(Q, va[b])) {
                 atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
-                if (live && claim(bits, va[b])) queue[atomicAdd(&s_tail, 1u)] = va[b];
+                if (live && claim(bits, va[b])) push(queue, &s_tail, A.qcap, va[b]);
               }
             } else if (live && claim(bits, va[b])) {
               // S is marked in the bitmap, so a live edge into S claims nothing
-              queue[atomicAdd(&s_tail, 1u)] = va[b];
+              push(queue, &s_tail, A.qcap, va[b]);
             }
           }
         }
@@ -1299,6 +1319,20 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       __syncthreads();
     }
     const uint32_t Y = s_tail;
+    if (Y > A.qcap) {
+      // outgrew the queue: nothing of the sample was recorded; it goes to
+      // the pass with full-size queues, and the whole bitmap is cleared
+      // (bits were set for nodes the queue could not hold)
+      if (tid == 0) {
+        if (!BWD && A.list3)
+          A.list3[atomicAdd(A.nlist3, 1u)] = f;
+        else
+          atomicOr(A.err, 16u);
+      }
+      for (int64_t w = tid; w < A.bits_words; w += LB) bits[w] = 0u;
+      __syncthreads();
+      continue;
+    }
     if (tid == 0) {
       if (BWD) {
         if (Y != y) atomicOr(A.err, 2u);

@@ -111,6 +111,11 @@ struct oi_graph {
   // per-launch workspaces
   DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_chunks, d_pairs, d_pacc, d_bits, d_queue;
   int large_blocks = 0;
+  uint32_t large_qcap = 0;          // queue entries per large-kernel block
+  DevBuf d_gbits, d_gqueue;         // full-size pool for samples that outgrow large_qcap
+  int giant_blocks = 0;
+  int small_direct = 0;             // 0: automatic, 1: always, 2: never (see oi_set_routing)
+  int64_t qcap_override = 0;        // > 0: queue entries per main-pool block
   int variant = 0;
   bool use_tiny = true;
   uint32_t chunk = 256;
@@ -118,7 +123,7 @@ struct oi_graph {
   uint64_t round_max = 1ull << 26;
   // timing
   bool timing = false;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
   oi_timing tm{};
 };
 
@@ -243,10 +248,16 @@ struct BwdBufs {
   unsigned long long *live = nullptr, *dead = nullptr, *tab = nullptr;
 };
 
+// Queue entries per block of the main large-kernel pool: min(n, 2^20).  A
+// sample that activates more nodes goes to a second pass over blocks with
+// n-entry queues, so the main pool can hold many blocks even for n = 1e8.
+constexpr int64_t kLargeQcap = 1 << 20;
+
 oi_status ensure_large_pool(oi_graph* g) {
   if (g->large_blocks > 0) return OI_OK;
   const int64_t words = (g->n + 31) / 32;
-  const double per = (double)words * 4.0 + (double)g->n * 4.0;
+  const int64_t qcap = std::min<int64_t>(g->n, g->qcap_override > 0 ? g->qcap_override : kLargeQcap);
+  const double per = (double)words * 4.0 + (double)qcap * 4.0;
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
   // one workspace per resident block of the large kernel (forward and
@@ -259,10 +270,30 @@ oi_status ensure_large_pool(oi_graph* g) {
   int blocks = (int)std::min<double>((double)occ * g->cus, std::floor(budget / per));
   if (blocks < 1) return fail(OI_ENOMEM, "no room for a large-cascade workspace");
   HIP_TRY(g->d_bits.ensure((size_t)blocks * (size_t)words * 4));
-  HIP_TRY(g->d_queue.ensure((size_t)blocks * (size_t)g->n * 4));
+  HIP_TRY(g->d_queue.ensure((size_t)blocks * (size_t)qcap * 4));
   HIP_TRY(hipMemsetAsync(g->d_bits.p, 0, (size_t)blocks * (size_t)words * 4, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
   g->large_blocks = blocks;
+  g->large_qcap = (uint32_t)qcap;
+  return OI_OK;
+}
+
+// The pool with n-entry queues, allocated on first need: up to 64 blocks
+// within a quarter of free memory and 32 GiB.
+oi_status ensure_giant_pool(oi_graph* g) {
+  if (g->giant_blocks > 0) return OI_OK;
+  const int64_t words = (g->n + 31) / 32;
+  const double per = (double)words * 4.0 + (double)g->n * 4.0;
+  size_t freeb = 0, totalb = 0;
+  HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+  const double budget = std::min(32.0 * (1ull << 30), 0.25 * (double)freeb);
+  int blocks = (int)std::min<double>(64.0, std::floor(budget / per));
+  if (blocks < 1) return fail(OI_ENOMEM, "no room for a full-size cascade workspace");
+  HIP_TRY(g->d_gbits.ensure((size_t)blocks * (size_t)words * 4));
+  HIP_TRY(g->d_gqueue.ensure((size_t)blocks * (size_t)g->n * 4));
+  HIP_TRY(hipMemsetAsync(g->d_gbits.p, 0, (size_t)blocks * (size_t)words * 4, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  g->giant_blocks = blocks;
   return OI_OK;
 }
 
@@ -301,7 +332,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   HIP_TRY(hipMemsetAsync(g->d_ctl.p, 0, 16 * sizeof(unsigned long long), g->stream));
 
   // control block: [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier sums,
-  // [11] counter2
+  // [11] counter2, [12] nlist3, [13] the second large pass's counter
   unsigned long long* ctl = g->d_ctl.as<unsigned long long>();
   oi::SampleLaunch A{};
   A.n = g->n;
@@ -324,13 +355,18 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   A.list2 = g->d_def2.as<unsigned long long>();
   A.nlist2 = reinterpret_cast<unsigned int*>(ctl + 3);
   A.small_from_list1 = g->use_tiny ? 1 : 0;
-  A.small_direct_max = (uint32_t)g->large_blocks;
+  A.small_direct_max = g->small_direct == 1 ? 0xFFFFFFFFu : (g->small_direct == 2 ? 0u : (uint32_t)g->large_blocks);
   A.err = reinterpret_cast<unsigned int*>(ctl + 4);
   A.chunk = g->chunk;
   A.tiny_chunk = g->tiny_chunk;
   A.bits = g->d_bits.as<uint32_t>();
   A.queue = g->d_queue.as<int32_t>();
   A.bits_words = (g->n + 31) / 32;
+  A.qcap = g->large_qcap;
+  A.queue_stride = (int64_t)g->large_qcap;
+  // list1's storage is free once the small kernel has run: it holds list3
+  A.list3 = g->d_def.as<unsigned long long>();
+  A.nlist3 = reinterpret_cast<unsigned int*>(ctl + 12);
   const bool is_bwd = bwd != nullptr;
   if (is_bwd) {
     A.y_in = bwd->y_in;
@@ -365,9 +401,32 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
   if (g->timing) HIP_TRY(hipEventRecord(g->ev[3], g->stream));
   unsigned long long hctl[16] = {0};
+  HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipStreamSynchronize(g->stream));
+  float giant_ms = 0.f;
+  if ((hctl[12] & 0xffffffffull) != 0 && (hctl[4] & 0xffffffffull) == 0) {
+    // samples that outgrew the main pool's queues: one more pass of the
+    // large kernel over list3 with n-entry queues (it cannot overflow)
+    OI_TRY(ensure_giant_pool(g));
+    oi::SampleLaunch B = A;
+    B.list2 = A.list3;
+    B.nlist2 = A.nlist3;
+    B.counter2 = ctl + 13;
+    B.bits = g->d_gbits.as<uint32_t>();
+    B.queue = g->d_gqueue.as<int32_t>();
+    B.qcap = (uint32_t)std::min<int64_t>(g->n, 0xFFFFFFFFll);
+    B.queue_stride = g->n;
+    B.list3 = nullptr;
+    B.nlist3 = nullptr;
+    if (g->timing) HIP_TRY(hipEventRecord(g->ev[4], g->stream));
+    HIP_TRY(oi::launch_large(is_bwd, B, g->giant_blocks, g->stream));
+    if (g->timing) HIP_TRY(hipEventRecord(g->ev[5], g->stream));
+    HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    if (g->timing) HIP_TRY(hipEventElapsedTime(&giant_ms, g->ev[4], g->ev[5]));
+  }
   HIP_TRY(hipMemcpyAsync(sums.data(), g->d_sums.p, sums.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                          g->stream));
-  HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
   const unsigned int err = (unsigned int)(hctl[4] & 0xffffffffull);
   if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
@@ -379,7 +438,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     HIP_TRY(hipEventElapsedTime(&t2, g->ev[2], g->ev[3]));
     g->tm.tiny_ms += t0;
     g->tm.small_ms += t1;
-    g->tm.large_ms += t2;
+    g->tm.large_ms += t2 + giant_ms;
     g->tm.launches += 1;
     g->tm.samples += total;
     g->tm.handed_small += hctl[2] & 0xffffffffull;
@@ -850,7 +909,7 @@ oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const in
   HIP_TRY(g->d_row_ptr.ensure(((size_t)n + 1) * 8));
   HIP_TRY(hipMemcpy(g->d_row_ptr.p, g->row_ptr.data(), ((size_t)n + 1) * 8, hipMemcpyHostToDevice));
   OI_TRY(upload_graph(g.get()));
-  for (int i = 0; i < 4; ++i) HIP_TRY(hipEventCreate(&g->ev[i]));
+  for (int i = 0; i < 6; ++i) HIP_TRY(hipEventCreate(&g->ev[i]));
   *out = g.release();
   return OI_OK;
 }
@@ -904,7 +963,7 @@ oi_status oi_set_stream(oi_graph* g, void* hip_stream) {
 void oi_graph_destroy(oi_graph* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 6; ++i)
     if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
   delete g;
 }
@@ -1083,6 +1142,20 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
     if (round_max % kChunk) return fail(OI_EINVAL, "round_max must be a multiple of 4096");
     if (round_max > (1ll << 31)) return fail(OI_ERANGE, "round_max above 2^31");
     g->round_max = (uint64_t)round_max;
+  }
+  return OI_OK;
+}
+
+oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (small_direct > 2) return fail(OI_EINVAL, "small_direct must be -1, 0, 1 or 2");
+  if (small_direct >= 0) g->small_direct = small_direct;
+  if (large_qcap > 0 && large_qcap != g->qcap_override) {
+    HIP_TRY(hipStreamSynchronize(g->stream));
+    g->qcap_override = large_qcap;
+    g->d_bits.release();
+    g->d_queue.release();
+    g->large_blocks = 0;
   }
   return OI_OK;
 }

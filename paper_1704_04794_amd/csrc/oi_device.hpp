@@ -82,9 +82,16 @@ struct SampleLaunch {
   uint32_t chunk;                  // samples the small kernel takes per counter increment
   uint32_t tiny_chunk;             // samples the tiny kernel takes per counter increment
   // large-cascade kernel workspace: per block a visited bitmap and a queue
+  // of qcap entries (queue_stride apart); a sample that activates more than
+  // qcap nodes is abandoned and its flat index appended to list3, for a
+  // second pass with blocks whose queues hold n entries
   uint32_t* bits;
   int32_t* queue;
   int64_t bits_words;
+  uint32_t qcap;
+  int64_t queue_stride;
+  unsigned long long* list3;       // null in that second pass
+  unsigned int* nlist3;
   // backward accumulators (null in the forward)
   const uint32_t* y_in;            // per-sample Y from the forward
   unsigned long long* acc_live;    // per edge: sum of Y over samples where the edge is revealed live

@@ -79,7 +79,8 @@ def test_null_handles_are_rejected():
     import paper_1704_04794_amd as P
     for call in (lambda: P.oi_gather_probe(None, 1024),
                  lambda: P.oi_timing_get(None),
-                 lambda: P.oi_set_tuning(None, 0)):
+                 lambda: P.oi_set_tuning(None, 0),
+                 lambda: P.oi_set_routing(None, 0)):
         with pytest.raises(P.OiError) as ei:
             call()
         assert ei.value.status == P._binding.OI_EINVAL

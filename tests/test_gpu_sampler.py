@@ -206,3 +206,31 @@ def test_few_handed_samples_go_straight_to_the_large_kernel(P):
     got = grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
     G.close()
+
+
+@pytest.mark.parametrize("small_direct,qcap", [(1, 24), (2, 24), (0, 1 << 20)])
+def test_routing_and_capped_queues_bit_exact(P, small_direct, qcap):
+    """Routing settings do not change results: hand-overs forced through or
+    around the small kernel, and large-kernel queues capped far below the
+    cascades so most large samples take the second pass with n-entry queues.
+    The backward under the same settings matches the oracle."""
+    import torch
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gw = g.with_p(wc_probs(g))
+    G = _gpu_graph(P, gw)
+    G.tune(small_direct=small_direct, large_qcap=qcap)
+    G.timing(True)
+    S = uniform_seed_set(gw, 5, 2)
+    _compare(P, gw, S, 20000, G=G, label=f"cl20k wc routing {small_direct} qcap {qcap}")
+    t = G.timing()
+    assert t["large_y"] > 0
+    if small_direct == 1:
+        assert t["small_y"] == 0
+    N = 20000
+    grad = torch.empty(gw.m, dtype=torch.float32, device="cuda")
+    G.backward(S, N, grad)
+    o = O.backward(gw, S, 0, RUN_SEED, 0, N)
+    ref = o["beta0"] * o["acc"] / N
+    got = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    G.close()
