@@ -204,6 +204,9 @@ def batched_vs_single(P, args):
     delta = extra["delta"]
     G = P.Graph.from_inputs(g)
     G.estimate(sub[0], 0.5, delta, query_id=int(qids[0]))  # warm up kernels and workspaces
+    t = time.perf_counter()
+    tune = G.autotune(sub, pilot=4096, query_ids=qids)
+    log(f"autotune ({time.perf_counter() - t:.1f}s): {tune}")
     import torch
     torch.cuda.synchronize()
     t = time.perf_counter()
@@ -222,7 +225,7 @@ def batched_vs_single(P, args):
             f"({k} uniform + {k} top-1% out-degree, |S| in [1,1000]), SOIEA eps={eps} delta={delta}",
             "batched_estimates_per_s": len(sub) / tb, "single_estimates_per_s": len(sub) / ts,
             "speedup": ts / tb, "identical_results": same, "samples": samples,
-            "batched_samples_per_s": samples / tb}
+            "batched_samples_per_s": samples / tb, "autotune": tune}
 
 
 def main():

@@ -202,6 +202,30 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
  * Changing large_qcap reallocates the pool.  Results do not depend on
  * either setting.  Errors: OI_EINVAL for a null graph or small_direct > 2. */
 oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
+/* What oi_autotune chose and measured. */
+typedef struct {
+  int32_t variant;      /* small-kernel variant */
+  int32_t tiny;         /* 1: the tiny kernel runs first */
+  int32_t small_direct; /* as in oi_set_routing */
+  int32_t candidates;   /* configurations timed */
+  int32_t seed_sets;    /* pilot seed sets (beta_0 > 0) */
+  int32_t pad;
+  double best_ms;       /* pilot launch time of the chosen configuration */
+  double default_ms;    /* ... of the default (tiny first, variant 0, automatic routing) */
+} oi_autotune_result;
+
+/* Sampler-schedule autotuner (a tuning aid; results never depend on it).
+ * Times one sampling launch of `pilot` samples (stream X, samples
+ * 0..pilot-1) of up to four of the nq seed sets (spread over the list, those
+ * with beta_0 = 0 skipped) under every combination of: the tiny kernel first
+ * or not, each small-kernel variant, and automatic or always-direct routing
+ * of hand-overs to the large kernel; then applies the fastest to the graph
+ * (as oi_set_tuning / oi_set_routing would).  Seed sets are given as in
+ * oi_estimate_batch.  pilot in [4096, round_max], else OI_ERANGE.  With no
+ * seed set of positive beta_0 nothing is timed or changed (candidates = 0).
+ * Uses the graph's Y workspace; blocks until done. */
+oi_status oi_autotune(oi_graph* g, int32_t nq, const int64_t* seed_off, const int32_t* seeds,
+                      const uint32_t* query_ids, uint64_t pilot, uint32_t run_seed, oi_autotune_result* out);
 int oi_num_variants(void);
 oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* ring_cap, int* rounds_per_pass);
 

@@ -9,7 +9,8 @@ from __future__ import annotations
 import numpy as np
 
 from ._binding import (  # noqa: F401
-    LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_backward, oi_gather_probe,
+    LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_autotune, oi_backward,
+    oi_gather_probe,
     oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
     oi_graph_set_theta, oi_last_error,
     oi_num_variants, oi_sample_fixed, oi_set_routing, oi_set_stream, oi_set_tuning, oi_stage1_table, oi_timing_enable,
@@ -101,6 +102,15 @@ class Graph:
         """Random-read bandwidth of this graph's CSR under the samplers' access
         pattern (no coins or visited sets): dict(useful_bytes, edges, ms, gbps)."""
         return oi_gather_probe(self.h, count, seed)
+
+    def autotune(self, seed_sets, pilot=1 << 16, query_ids=None, run_seed=RUN_SEED):
+        """Time the sampler's schedules on a pilot of up to four of the seed
+        sets and keep the fastest (results never depend on the choice)."""
+        off = np.zeros(len(seed_sets) + 1, np.int64)
+        off[1:] = np.cumsum([len(s) for s in seed_sets])
+        seeds = np.concatenate([np.asarray(s, np.int32) for s in seed_sets]) if seed_sets else np.zeros(0, np.int32)
+        q = np.arange(len(seed_sets), dtype=np.uint32) if query_ids is None else np.asarray(query_ids, np.uint32)
+        return oi_autotune(self.h, off, seeds, q, pilot, run_seed)
 
     def timing(self, enable=None):
         if enable is not None:

@@ -38,6 +38,15 @@ class oi_result(C.Structure):
         return d
 
 
+class oi_autotune_result(C.Structure):
+    _fields_ = [("variant", C.c_int32), ("tiny", C.c_int32), ("small_direct", C.c_int32),
+                ("candidates", C.c_int32), ("seed_sets", C.c_int32), ("pad", C.c_int32),
+                ("best_ms", C.c_double), ("default_ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_ if k != "pad"}
+
+
 class oi_timing(C.Structure):
     _fields_ = [
         ("tiny_ms", C.c_double), ("small_ms", C.c_double), ("large_ms", C.c_double),
@@ -84,6 +93,7 @@ def _load():
         "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
         "oi_gather_probe": [vp, u64, u32, P(u64), P(u64), P(dbl)],
         "oi_set_routing": [vp, ci, i64],
+        "oi_autotune": [vp, i32, vp, vp, vp, u64, u32, P(oi_autotune_result)],
     }
     for name, args in sig.items():
         f = getattr(L, name)
@@ -241,6 +251,16 @@ def oi_set_tuning(g, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1)
 
 def oi_set_routing(g, small_direct=-1, large_qcap=-1):
     _check("oi_set_routing", _lib.oi_set_routing(g, int(small_direct), int(large_qcap)))
+
+
+def oi_autotune(g, seed_off, seeds, query_ids, pilot, run_seed):
+    off = _host(seed_off, np.int64)
+    s = _host(seeds, np.int32)
+    q = _host(query_ids, np.uint32)
+    r = oi_autotune_result()
+    _check("oi_autotune", _lib.oi_autotune(g, int(off.size - 1), _ptr(off), _ptr(s), _ptr(q), int(pilot),
+                                           int(run_seed) & 0xFFFFFFFF, C.byref(r)))
+    return r.as_dict()
 
 
 def oi_num_variants():

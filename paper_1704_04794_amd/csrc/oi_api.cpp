@@ -9,6 +9,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1143,6 +1144,87 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
     if (round_max > (1ll << 31)) return fail(OI_ERANGE, "round_max above 2^31");
     g->round_max = (uint64_t)round_max;
   }
+  return OI_OK;
+}
+
+oi_status oi_autotune(oi_graph* g, int32_t nq, const int64_t* seed_off, const int32_t* seeds,
+                      const uint32_t* query_ids, uint64_t pilot, uint32_t run_seed, oi_autotune_result* out) {
+  if (!g || !seed_off || !seeds || !query_ids || !out) return fail(OI_EINVAL, "null argument");
+  if (nq < 1) return fail(OI_EINVAL, "need at least one seed set");
+  if (pilot < kChunk || pilot > g->round_max) return fail(OI_ERANGE, "pilot must be in [4096, round_max]");
+  *out = oi_autotune_result{};
+  // up to four seed sets spread over the list, skipping those with beta_0 = 0
+  std::vector<std::unique_ptr<HostQuery>> qs;
+  const int want = std::min<int32_t>(nq, 4);
+  for (int j = 0; j < want; ++j) {
+    const int32_t i = (int32_t)(((int64_t)j * nq) / want);
+    if (seed_off[i + 1] < seed_off[i]) return fail(OI_EINVAL, "seed_off must be non-decreasing");
+    std::unique_ptr<HostQuery> Q(new HostQuery());
+    Q->qid = query_ids[i];
+    OI_TRY(build_table(g, seeds + seed_off[i], seed_off[i + 1] - seed_off[i], *Q));
+    if (Q->beta0 > 0.0) {
+      OI_TRY(upload_query(g, *Q));
+      qs.push_back(std::move(Q));
+    }
+  }
+  const int saved_variant = g->variant, saved_direct = g->small_direct;
+  const bool saved_tiny = g->use_tiny;
+  if (qs.empty()) return OI_OK;
+  std::vector<const HostQuery*> qv;
+  std::vector<SegReq> segs;
+  for (size_t i = 0; i < qs.size(); ++i) {
+    qv.push_back(qs[i].get());
+    segs.push_back(SegReq{(uint32_t)i, 0u, 0ull, pilot, (uint64_t)i * pilot});
+  }
+  HIP_TRY(g->d_y.ensure((size_t)(qs.size() * pilot) * 4));
+  uint32_t* ybuf = g->d_y.as<uint32_t>();
+  std::vector<unsigned long long> sums;
+  auto run_ms = [&](double* ms) -> oi_status {
+    const auto t0 = std::chrono::steady_clock::now();
+    OI_TRY(run_sampler(g, qv, segs, run_seed, ybuf, nullptr, sums, nullptr, nullptr));
+    *ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    return OI_OK;
+  };
+  double best = 0.0, ms = 0.0;
+  int bv = 0, bt = 1, bd = 0, tried = 0;
+  g->use_tiny = true;
+  g->variant = 0;
+  g->small_direct = 0;
+  oi_status st = run_ms(&ms);  // warm-up of workspaces and code
+  for (int tiny = 1; st == OI_OK && tiny >= 0; --tiny) {
+    for (int v = 0; st == OI_OK && v < oi::num_small_variants(); ++v) {
+      for (int d = 0; st == OI_OK && d <= 1; ++d) {
+        g->use_tiny = tiny != 0;
+        g->variant = v;
+        g->small_direct = d;
+        st = run_ms(&ms);
+        if (st != OI_OK) break;
+        ++tried;
+        if (tiny == 1 && v == 0 && d == 0) out->default_ms = ms;
+        if (tried == 1 || ms < best) {
+          best = ms;
+          bv = v;
+          bt = tiny;
+          bd = d;
+        }
+      }
+    }
+  }
+  if (st != OI_OK) {
+    g->variant = saved_variant;
+    g->use_tiny = saved_tiny;
+    g->small_direct = saved_direct;
+    return st;
+  }
+  g->variant = bv;
+  g->use_tiny = bt != 0;
+  g->small_direct = bd;
+  out->variant = bv;
+  out->tiny = bt;
+  out->small_direct = bd;
+  out->candidates = tried;
+  out->seed_sets = (int32_t)qs.size();
+  out->best_ms = best;
   return OI_OK;
 }
 

@@ -109,3 +109,23 @@ def test_rsa_rejects_bad_parameters(P):
     with pytest.raises(P.OiError):
         G.estimate([0], 0.1, 0.1, mode=2)
     G.close()
+
+
+def test_autotune_keeps_results(P):
+    """The autotuner times every schedule on a pilot and applies the fastest;
+    batched estimates before and after it are identical."""
+    import numpy as np
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gw = g.with_p(wc_probs(g))
+    sets = [uniform_seed_set(gw, k, 30 + k) for k in (1, 5, 40)]
+    G = P.Graph.from_inputs(gw)
+    before = G.estimate_batch(sets, 0.2, 0.01)
+    r = G.autotune(sets, pilot=8192)
+    nv = P.oi_num_variants()
+    assert r["candidates"] == 2 * 2 * nv and r["seed_sets"] == 3
+    assert 0 <= r["variant"] < nv and r["tiny"] in (0, 1) and r["small_direct"] in (0, 1)
+    assert 0 < r["best_ms"] <= r["default_ms"]
+    after = G.estimate_batch(sets, 0.2, 0.01)
+    for a, b in zip(before, after):
+        assert a["oi"] == b["oi"] and a["T"] == b["T"] and a["samples_x"] == b["samples_x"]
+    G.close()
