@@ -1114,9 +1114,11 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
 // LBN nodes' row bounds, a block scan lays the batch's edge groups out in one
 // index space, and thread t takes groups t, t + LB, ... of it.  After the
 // sample the bits it set (the queue and S) are cleared again.
-constexpr int LB = 256;
-constexpr int LBN = 4;  // queued nodes per thread per expansion batch
+constexpr int LB = 256;        // threads of a main-pool block
+constexpr int LB_FULL = 1024;  // threads of a block of the full-queue pass (few, very large samples)
+constexpr int LBN = 4;         // queued nodes per thread per expansion batch
 
+template <int NT>
 __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, int tid, uint32_t* total) {
   const int lane = tid & 63, wid = tid >> 6;
   x = wave_incl_scan(x, lane);
@@ -1124,7 +1126,7 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, 
   __syncthreads();
   uint32_t add = 0, tot = 0;
 #pragma unroll
-  for (int w = 0; w < LB / 64; ++w) {
+  for (int w = 0; w < NT / 64; ++w) {
     const uint32_t v = wtot[w];
     if (w < wid) add += v;
     tot += v;
@@ -1135,6 +1137,7 @@ __device__ __forceinline__ uint32_t block_incl_scan(uint32_t x, uint32_t* wtot, 
 }
 
 // Sets (set = true) or clears the bits of the seed set in a block's bitmap.
+template <int NT>
 __device__ __forceinline__ void mark_seed_set(const QueryDev& Q, uint32_t* bits, bool set, int tid) {
   if (Q.k == 1) {
     if (tid == 0) {
@@ -1145,7 +1148,7 @@ __device__ __forceinline__ void mark_seed_set(const QueryDev& Q, uint32_t* bits,
     }
     return;
   }
-  for (uint32_t h = tid; h <= Q.smask; h += LB) {
+  for (uint32_t h = tid; h <= Q.smask; h += NT) {
     const int32_t v = gptr(Q.shash)[h];
     if (v >= 0) {
       if (set)
@@ -1170,14 +1173,14 @@ __device__ __forceinline__ void push(int32_t* queue, uint32_t* tail, uint32_t qc
   if (pos < qcap) queue[pos] = v;
 }
 
-template <bool BWD>
-__global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
+template <bool BWD, int NT>
+__global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_tail;
   __shared__ unsigned long long s_E;
-  __shared__ uint32_t wtot[LB / 64];
-  __shared__ uint32_t it_scan[LB * LBN];
-  __shared__ uint32_t it_eb[LB * LBN];
-  __shared__ uint32_t it_ee[LB * LBN];
+  __shared__ uint32_t wtot[NT / 64];
+  __shared__ uint32_t it_scan[NT * LBN];
+  __shared__ uint32_t it_eb[NT * LBN];
+  __shared__ uint32_t it_ee[NT * LBN];
   __shared__ int64_t s_i;
   __shared__ uint32_t s_di;
   const int tid = threadIdx.x;
@@ -1208,7 +1211,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       __syncthreads();
       continue;
     }
-    mark_seed_set(Q, bits, true, tid);
+    mark_seed_set<NT>(Q, bits, true, tid);
     __syncthreads();
     if (tid == 0) {
       int64_t i = select_entry(Q, A.seed, S.stream, s);
@@ -1228,7 +1231,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
     const int64_t i = s_i;
     // Stage 1, lines 4-6 of Alg. 1
     const int64_t gend = (Q.l + 3) >> 2;
-    for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += LB) {
+    for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += NT) {
       const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
       const TabGroup T = load_tab(Q.tab, g);
 #pragma unroll
@@ -1241,7 +1244,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       }
     }
     __syncthreads();
-    // Stage 2, lines 7-12: expand the queue in batches of up to LB * LBN
+    // Stage 2, lines 7-12: expand the queue in batches of up to NT * LBN
     // nodes, LBN consecutive queue entries per thread (their row reads are
     // independent, so they are in flight together)
     uint32_t head = 0;
@@ -1249,7 +1252,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       const uint32_t tail = s_tail;
       __syncthreads();
       if (head >= tail || tail > A.qcap) break;
-      const uint32_t nb = tail - head < (uint32_t)(LB * LBN) ? tail - head : (uint32_t)(LB * LBN);
+      const uint32_t nb = tail - head < (uint32_t)(NT * LBN) ? tail - head : (uint32_t)(NT * LBN);
       uint32_t rb[LBN], re[LBN], part[LBN];
       uint32_t mine = 0;
       unsigned long long eloc = 0;
@@ -1271,7 +1274,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       }
       if (eloc) atomicAdd(&s_E, eloc);
       uint32_t total;
-      const uint32_t base = block_incl_scan(mine, wtot, tid, &total) - mine;
+      const uint32_t base = block_incl_scan<NT>(mine, wtot, tid, &total) - mine;
 #pragma unroll
       for (int k = 0; k < LBN; ++k) {
         const uint32_t j = (uint32_t)(LBN * tid + k);
@@ -1280,37 +1283,58 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         it_ee[j] = re[k];
       }
       __syncthreads();
-      for (uint32_t t = tid; t < total; t += LB) {
-        int lo = 0, hi = (int)nb - 1;  // first entry whose groups end after t
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (it_scan[mid] > t)
-            hi = mid;
-          else
-            lo = mid + 1;
-        }
-        const uint32_t before = lo ? it_scan[lo - 1] : 0u;
-        const uint32_t lo_e = it_eb[lo], hi_e = it_ee[lo];
-        const uint32_t g = (lo_e >> 2) + (t - before);
-        const Words d = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, g);
-        const OI_GLOBAL char* q = (const OI_GLOBAL char*)(gptr(A.eg) + g);
-        const v4i32 va = *(const OI_GLOBAL v4i32*)q;
-        const v4i32 pa = *(const OI_GLOBAL v4i32*)(q + 16);
-        const float pb[4] = {__int_as_float(pa.x), __int_as_float(pa.y), __int_as_float(pa.z), __int_as_float(pa.w)};
+      // two groups per thread per step, so that their loads and coin
+      // blocks are in flight together
+      for (uint32_t t0 = tid; t0 < total; t0 += 2 * NT) {
+        uint32_t gg[2], lo_e[2], hi_e[2];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const uint32_t e = 4 * g + b;
-          if (e >= lo_e && e < hi_e) {
-            const bool live = edge_live(d.w[b], pb[b]);
-            if (BWD) {
-              // an edge into S is never revealed (its target is not outside S)
-              if (!in_seed_set(Q, va[b])) {
-                atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
-                if (live && claim(bits, va[b])) push(queue, &s_tail, A.qcap, va[b]);
+        for (int u = 0; u < 2; ++u) {
+          const uint32_t t = t0 + (uint32_t)u * NT;
+          gg[u] = 0;
+          lo_e[u] = hi_e[u] = 0;  // no edge of group 0 is in [0, 0)
+          if (t < total) {
+            int lo = 0, hi = (int)nb - 1;  // first entry whose groups end after t
+            while (lo < hi) {
+              const int mid = (lo + hi) >> 1;
+              if (it_scan[mid] > t)
+                hi = mid;
+              else
+                lo = mid + 1;
+            }
+            const uint32_t before = lo ? it_scan[lo - 1] : 0u;
+            lo_e[u] = it_eb[lo];
+            hi_e[u] = it_ee[lo];
+            gg[u] = (lo_e[u] >> 2) + (t - before);
+          }
+        }
+        Words d[2];
+        v4i32 va[2], pa[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const OI_GLOBAL char* q = (const OI_GLOBAL char*)(gptr(A.eg) + gg[u]);
+          va[u] = *(const OI_GLOBAL v4i32*)q;
+          pa[u] = *(const OI_GLOBAL v4i32*)(q + 16);
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) d[u] = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, gg[u]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const uint32_t e = 4 * gg[u] + b;
+            if (e >= lo_e[u] && e < hi_e[u]) {
+              const bool live = edge_live(d[u].w[b], __int_as_float(pa[u][b]));
+              const int32_t v = va[u][b];
+              if (BWD) {
+                // an edge into S is never revealed (its target is not outside S)
+                if (!in_seed_set(Q, v)) {
+                  atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
+                  if (live && claim(bits, v)) push(queue, &s_tail, A.qcap, v);
+                }
+              } else if (live && claim(bits, v)) {
+                // S is marked in the bitmap, so a live edge into S claims nothing
+                push(queue, &s_tail, A.qcap, v);
               }
-            } else if (live && claim(bits, va[b])) {
-              // S is marked in the bitmap, so a live edge into S claims nothing
-              push(queue, &s_tail, A.qcap, va[b]);
             }
           }
         }
@@ -1329,7 +1353,7 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
         else
           atomicOr(A.err, 16u);
       }
-      for (int64_t w = tid; w < A.bits_words; w += LB) bits[w] = 0u;
+      for (int64_t w = tid; w < A.bits_words; w += NT) bits[w] = 0u;
       __syncthreads();
       continue;
     }
@@ -1345,9 +1369,9 @@ __global__ void __launch_bounds__(LB) large_kernel(SampleLaunch A) {
       atomicAdd(&A.tier_sums[4], (unsigned long long)Y);
       atomicAdd(&A.tier_sums[5], s_E);
     }
-    for (uint32_t t = tid; t < Y; t += LB) bits[queue[t] >> 5] = 0u;
+    for (uint32_t t = tid; t < Y; t += NT) bits[queue[t] >> 5] = 0u;
     __syncthreads();
-    mark_seed_set(Q, bits, false, tid);
+    mark_seed_set<NT>(Q, bits, false, tid);
     __syncthreads();
   }
 }
@@ -1688,15 +1712,24 @@ hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t 
 hipError_t large_occupancy(bool bwd, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks_per_cu,
-      bwd ? reinterpret_cast<const void*>(&large_kernel<true>) : reinterpret_cast<const void*>(&large_kernel<false>),
+      bwd ? reinterpret_cast<const void*>(&large_kernel<true, LB>)
+          : reinterpret_cast<const void*>(&large_kernel<false, LB>),
       LB, 0);
 }
 
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
   if (bwd)
-    hipLaunchKernelGGL(large_kernel<true>, dim3(blocks), dim3(LB), 0, st, A);
+    hipLaunchKernelGGL((large_kernel<true, LB>), dim3(blocks), dim3(LB), 0, st, A);
   else
-    hipLaunchKernelGGL(large_kernel<false>, dim3(blocks), dim3(LB), 0, st, A);
+    hipLaunchKernelGGL((large_kernel<false, LB>), dim3(blocks), dim3(LB), 0, st, A);
+  return hipGetLastError();
+}
+
+hipError_t launch_large_full(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
+  if (bwd)
+    hipLaunchKernelGGL((large_kernel<true, LB_FULL>), dim3(blocks), dim3(LB_FULL), 0, st, A);
+  else
+    hipLaunchKernelGGL((large_kernel<false, LB_FULL>), dim3(blocks), dim3(LB_FULL), 0, st, A);
   return hipGetLastError();
 }
 

@@ -27,6 +27,7 @@ hipError_t small_occupancy(int v, bool bwd, int* blocks_per_cu);
 hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t large_occupancy(bool bwd, int* blocks_per_cu);
+hipError_t launch_large_full(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 int tiny_cap();
 hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu);
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
@@ -280,7 +281,8 @@ oi_status ensure_large_pool(oi_graph* g) {
 }
 
 // The pool with n-entry queues, allocated on first need: up to 64 blocks
-// within a quarter of free memory and 32 GiB.
+// (of 1024 threads: its samples are the largest) within a quarter of free
+// memory and 32 GiB.
 oi_status ensure_giant_pool(oi_graph* g) {
   if (g->giant_blocks > 0) return OI_OK;
   const int64_t words = (g->n + 31) / 32;
@@ -420,7 +422,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     B.list3 = nullptr;
     B.nlist3 = nullptr;
     if (g->timing) HIP_TRY(hipEventRecord(g->ev[4], g->stream));
-    HIP_TRY(oi::launch_large(is_bwd, B, g->giant_blocks, g->stream));
+    HIP_TRY(oi::launch_large_full(is_bwd, B, g->giant_blocks, g->stream));
     if (g->timing) HIP_TRY(hipEventRecord(g->ev[5], g->stream));
     HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
