@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       if (BWD) {
         if (cnt != y) atomicOr(A.err, 2u);
       } else {
-        A.y_out[oidx] = cnt;
+        if (A.y_out) A.y_out[oidx] = cnt;
         if (A.e_out) A.e_out[oidx] = E;
       }
       if (sg != acc_seg) {
@@ -1072,7 +1072,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
           if (BWD) {
             if (cnt != W.s_y[k]) atomicOr(A.err, 2u);
           } else {
-            A.y_out[idx] = cnt;
+            if (A.y_out) A.y_out[idx] = cnt;
             if (A.e_out) A.e_out[idx] = E;
           }
           W.s_active[k] = 0;
@@ -1361,7 +1361,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       if (BWD) {
         if (Y != y) atomicOr(A.err, 2u);
       } else {
-        A.y_out[oidx] = Y;
+        if (A.y_out) A.y_out[oidx] = Y;
         if (A.e_out) A.e_out[oidx] = s_E;
       }
       atomicAdd(&A.seg_sums[2 * sg], (unsigned long long)Y);
@@ -1449,21 +1449,42 @@ __global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const P
       continue;
     }
     unsigned long long lo = 0, hi = 0;
-    // four independent loads in flight per thread
-    for (uint64_t i = lo_pair + threadIdx.x; i < hi_pair; i += 4 * 256) {
-      uint2 v[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const uint64_t ii = i + (uint64_t)u * 256;
-        v[u] = make_uint2(0u, 0u);
-        if (ii < hi_pair) v[u] = *reinterpret_cast<const uint2*>(&y[P.out_off + 2 * (ii - P.flat0)]);
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const unsigned long long d =
-            v[u].x > v[u].y ? (unsigned long long)(v[u].x - v[u].y) : (unsigned long long)(v[u].y - v[u].x);
+    // local pair indices [a, b) of this segment; pairs 2k and 2k + 1 sit in
+    // one 16-byte-aligned group of four Y values (out_off is 4096-aligned)
+    uint64_t a = lo_pair - P.flat0;
+    const uint64_t b = hi_pair - P.flat0;
+    const uint32_t* yb = y + P.out_off;
+    if ((a & 1) && a < b) {  // a leading odd pair
+      if (threadIdx.x == 0) {
+        const uint2 v = *reinterpret_cast<const uint2*>(&yb[2 * a]);
+        const unsigned long long d = v.x > v.y ? (unsigned long long)(v.x - v.y) : (unsigned long long)(v.y - v.x);
         add128(lo, hi, d * d, 0);
       }
+      ++a;
+    }
+    const uint64_t q0 = a >> 1, q1 = b >> 1;  // whole groups of two pairs
+    for (uint64_t q = q0 + threadIdx.x; q < q1; q += 2 * 256) {
+      uint4 v[2];
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint64_t qq = q + (uint64_t)u * 256;
+        v[u] = make_uint4(0u, 0u, 0u, 0u);
+        if (qq < q1) v[u] = *reinterpret_cast<const uint4*>(&yb[4 * qq]);
+      }
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const unsigned long long d0 =
+            v[u].x > v[u].y ? (unsigned long long)(v[u].x - v[u].y) : (unsigned long long)(v[u].y - v[u].x);
+        const unsigned long long d1 =
+            v[u].z > v[u].w ? (unsigned long long)(v[u].z - v[u].w) : (unsigned long long)(v[u].w - v[u].z);
+        add128(lo, hi, d0 * d0, 0);
+        add128(lo, hi, d1 * d1, 0);
+      }
+    }
+    if ((b & 1) && 2 * q1 >= a && threadIdx.x == 0) {  // a trailing odd pair
+      const uint2 v = *reinterpret_cast<const uint2*>(&yb[2 * (b - 1)]);
+      const unsigned long long d = v.x > v.y ? (unsigned long long)(v.x - v.y) : (unsigned long long)(v.y - v.x);
+      add128(lo, hi, d * d, 0);
     }
 #pragma unroll
     for (int sh = 32; sh > 0; sh >>= 1) {
@@ -1744,7 +1765,7 @@ hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, uns
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
                           hipStream_t st) {
   if (total == 0) return hipSuccess;
-  const uint64_t per_block = 8192;  // pairs per block: 64 KB of Y
+  const uint64_t per_block = 16384;  // pairs per block: 128 KB of Y
   const uint64_t blocks = (total + per_block - 1) / per_block;
   hipLaunchKernelGGL(pair_sq_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y,
                      reinterpret_cast<const PairSeg*>(ps), nps, total, per_block, acc);

@@ -98,6 +98,7 @@ struct DevBuf {
 
 constexpr uint32_t kChunk = 4096;        // Y values per chunk sum (stopping-rule bookkeeping)
 constexpr uint64_t kMaxSample = 1ull << 59;
+constexpr uint64_t kStep3Rounds = 4;     // a step-3-only round may hold this many round_max
 
 }  // namespace
 
@@ -601,9 +602,14 @@ uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 // kChunk in the round buffer so one chunk-sum launch covers all of them.
 oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
   HIP_TRY(g->d_y.ensure((size_t)g->round_max * 4));
-  const uint64_t cap = g->round_max;
   for (int guard = 0;; ++guard) {
     if (guard > 10000000) return fail(OI_ESTATE, "stopping rule did not converge");
+    // Step 3 needs only the sum of X_1..X_T, no per-sample Y: a round whose
+    // queries are all in step 3 writes no Y and may be kStep3Rounds times
+    // larger (fewer launches and host round trips)
+    bool all3 = true;
+    for (const Rsa& R : rs) all3 &= R.phase == P_DONE || R.phase == P_STEP3;
+    const uint64_t cap = all3 ? g->round_max * kStep3Rounds : g->round_max;
     std::vector<int> owner;
     std::vector<uint64_t> want;
     for (size_t i = 0; i < rs.size(); ++i) {
@@ -658,11 +664,13 @@ oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
     }
     std::vector<unsigned long long> sums;
     int launches = 0;
-    OI_TRY(run_sampler(g, qv, segs, seed, g->d_y.as<uint32_t>(), nullptr, sums, nullptr, &launches));
+    OI_TRY(run_sampler(g, qv, segs, seed, all3 ? nullptr : g->d_y.as<uint32_t>(), nullptr, sums, nullptr,
+                       &launches));
     uint32_t* ydev = g->d_y.as<uint32_t>();
     // chunk sums over the whole round buffer (used by X segments)
     bool any_x = false;
     for (const SegReq& sq : segs) any_x |= sq.stream == 0;
+    any_x &= !all3;
     std::vector<unsigned long long> ch;
     if (any_x) {
       const uint64_t nch = (off + kChunk - 1) / kChunk;
@@ -714,8 +722,11 @@ oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
         if (R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
         continue;
       }
-      const uint64_t c0 = sq.out_off / kChunk, nc = (sq.count + kChunk - 1) / kChunk;
-      std::vector<unsigned long long> mine(ch.begin() + (long)c0, ch.begin() + (long)(c0 + nc));
+      std::vector<unsigned long long> mine;
+      if (!all3) {
+        const uint64_t c0 = sq.out_off / kChunk, nc = (sq.count + kChunk - 1) / kChunk;
+        mine.assign(ch.begin() + (long)c0, ch.begin() + (long)(c0 + nc));
+      }
       if (R.phase == P_STEP1) {
         bool found = false;
         OI_TRY(scan_crossing(g, R, mine, R.nx, sq.count, ydev + sq.out_off, &found));
@@ -727,8 +738,7 @@ oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
           OI_TRY(after_step1(R));
           if (R.phase == P_STEP2 && R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
         }
-      } else {  // step 3 extends stream X up to T
-        R.xchunks.insert(R.xchunks.end(), mine.begin(), mine.end());
+      } else {  // step 3 extends stream X up to T (its chunk sums are never needed)
         R.nx += sq.count;
         R.hx += sums[2 * i];
         R.r.samples_x += sq.count;

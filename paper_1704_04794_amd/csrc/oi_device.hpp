@@ -65,7 +65,7 @@ struct SampleLaunch {
   int32_t nseg;
   uint64_t total;
   uint32_t seed;
-  uint32_t* y_out;                 // per sample Y
+  uint32_t* y_out;                 // per sample Y (null: only the per-segment sums are wanted)
   uint64_t* e_out;                 // per sample E (optional)
   unsigned long long* seg_sums;    // 2 per segment: sum Y, sum E
   unsigned long long* tier_sums;   // 2 per kernel (tiny, small, large): sum Y, sum E it finished
