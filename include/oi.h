@@ -188,7 +188,7 @@ oi_status oi_timing_get(oi_graph* g, oi_timing* out);
  * the one-sample-per-lane kernel first (default), 0 to start every sample in
  * the small kernel; tiny_chunk: samples the tiny kernel takes per increment
  * (0 = automatic, the default; negative keeps the current setting);
- * round_max: samples per sampling launch (multiple of 4096).  Negative (or
+ * round_max: samples per sampling launch (multiple of 4096, default 2^28).  Negative (or
  * zero) values keep the current setting.  Results do not depend on any of
  * these. */
 oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_chunk, int64_t round_max);

@@ -98,7 +98,7 @@ struct DevBuf {
 
 constexpr uint32_t kChunk = 4096;        // Y values per chunk sum (stopping-rule bookkeeping)
 constexpr uint64_t kMaxSample = 1ull << 59;
-constexpr uint64_t kStep3Rounds = 4;     // a step-3-only round may hold this many round_max
+constexpr uint64_t kStep3Rounds = 2;     // a step-3-only round may hold this many round_max
 
 }  // namespace
 
@@ -123,7 +123,7 @@ struct oi_graph {
   bool use_tiny = true;
   uint32_t chunk = 256;
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
-  uint64_t round_max = 1ull << 26;
+  uint64_t round_max = 1ull << 28;  // samples per launch: 1 GiB of Y, 2 GiB per hand-over list
   // timing
   bool timing = false;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
