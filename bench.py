@@ -70,9 +70,16 @@ def cpu_baseline(g, S, seconds):
     t = time.perf_counter()
     r = O.sample_fixed(g, S, 0, RUN_SEED, 0, 0, N, want_y=False, nthreads=nt)
     dt = time.perf_counter() - t
+    # the same oracle on one thread, over a slice of about 4 s
+    n1 = max(n0 // 4, int(N / nt * 4.0 / max(dt, 1e-6)))
+    t = time.perf_counter()
+    O.sample_fixed(g, S, 0, RUN_SEED, 0, 0, n1, want_y=False, nthreads=1)
+    dt1 = time.perf_counter() - t
     return {"value": N / dt, "unit": "samples/s", "cores": nt, "kind": "oracle",
             "sample": f"IICP samples 0..{N - 1} of stream X of the same query (fixed count, oracle in C, "
-                      f"{nt} threads), {dt:.1f} s; GTEPS {r['sum_e'] / dt / 1e9:.4f}"}
+                      f"{nt} threads), {dt:.1f} s; GTEPS {r['sum_e'] / dt / 1e9:.4f}; one thread: "
+                      f"{n1} samples in {dt1:.1f} s",
+            "one_thread_value": n1 / dt1}
 
 
 def gather_roofline(G, count=1 << 26, reps=3):
@@ -158,6 +165,17 @@ def billion_edge(P, args):
                "kernel_ms": {k: tm[f"{k}_ms"] for k in ("tiny", "small", "large")}}
         out["fixed"].append(row)
         log(f"fixed |S|={len(S)}: {row}")
+    # one SIEA estimate of the |S| = 1 set at the paper's default accuracy
+    # (eps = 0.1, delta = 1/n), for comparison with its runtimes on graphs of
+    # this size
+    S = sets[0]
+    t = time.perf_counter()
+    r = G.estimate(S, 0.1, 1.0 / g.n, mode=P.OI_MODE_SIEA, query_id=0)
+    dt = time.perf_counter() - t
+    out["siea_estimate"] = {"k": int(len(S)), "eps": 0.1, "delta": 1.0 / g.n, "seconds": dt, "is": r["is_"],
+                            "oi": r["oi"], "samples": r["samples_x"] + r["samples_xp"], "rounds": r["rounds"],
+                            "samples_per_s": (r["samples_x"] + r["samples_xp"]) / dt}
+    log(f"SIEA estimate: {out['siea_estimate']}")
     S = sets[2]
     N = 1 << 14
     grad = torch.empty(g.m, dtype=torch.float32, device="cuda")
