@@ -35,10 +35,10 @@ BYTES_PER_EDGE = 8   # col (int32) + p (fp32) per examined edge
 
 # HBM bytes per tiny_kernel launch on the default workload, from two
 # rocprofv3 counter passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the scales a
-# 1 GiB device copy gives those counters), mean over the 83 launches of one
+# 1 GiB device copy gives those counters), mean over the 20 launches of one
 # estimate.  Reported only while the kernel sources hash to what was measured.
-TRAFFIC = {"sources_sha1": "9da15dee02b00053a977eefb6e2d4c2ec3112153", "kernel": "tiny_kernel",
-           "bytes_per_launch": 270563635.2, "l2_hit_rate": 0.778}
+TRAFFIC = {"sources_sha1": "ccce7a80cc5e2a04ce0f4a032fa5aa658bb8fbc8", "kernel": "tiny_kernel",
+           "bytes_per_launch": 895727001.6, "l2_hit_rate": 0.785}
 KERNEL_SOURCES = ("paper_1704_04794_amd/csrc/iicp_kernels.hip", "paper_1704_04794_amd/csrc/oi_device.hpp")
 
 
