@@ -71,7 +71,7 @@ typedef struct {
                               the selected one) + (out-degree of every activated node) */
   int64_t k;          /* |S| after removing duplicate seeds */
   int64_t l;          /* |N^out_S|, the size of the Stage-1 table */
-  int32_t gsra_only;  /* 1 if eps >= 1/4 (RSA reduces to GSRA, Alg. 3 lines 1-2) */
+  int32_t gsra_only;  /* 1 if eps >= 1/4 (RSA reduces to GSRA, Alg. 3) */
   int32_t early;      /* 1 if the first GSRA returned its lower bound without sampling */
   int32_t status;     /* per-query oi_status (batch calls) */
   int32_t rounds;     /* sampling launches used */

@@ -254,7 +254,7 @@ static int scratch_init(oo_scratch *w, int64_t n)
 }
 static void scratch_free(oo_scratch *w) { free(w->vis); free(w->queue); }
 
-/* R6: Stage 1, line 2 of Alg. 1 */
+/* R6: Alg. 1, Stage 1: the first activated table entry */
 static int64_t select_first(const oo_table *t, double U)
 {
     double x = U * t->beta0;
@@ -306,15 +306,15 @@ static uint32_t iicp_sample(const oo_graph *g, const oo_table *t, uint32_t qid,
                             uint64_t *E_out, int64_t *sel, oo_scratch *w)
 {
     const uint8_t *inS = t->inS;
-    /* Stage 1, line 2 */
+    /* Stage 1: select the first activated entry i */
     int64_t i = select_first(t, selection_uniform(qid, seed, stream, s));
-    /* line 3: R <- {v_i}, Y = 1, mark v_i (S is marked through inS) */
+    /* R <- {v_i}, Y = 1, mark v_i (S is marked through inS) */
     int64_t head = 0, tail = 0;
     uint32_t Y = 1;
     uint64_t E = (uint64_t)(t->l - 1 - i);
     w->queue[tail++] = t->v[i];
     w->vis[t->v[i]] = 1;
-    /* lines 4-6 */
+    /* Stage 1: one coin for each later entry j > i */
     for (int64_t j = i + 1; j < t->l; ++j) {
         if (stage1_coin(qid, seed, stream, s, t, j)) {
             w->queue[tail++] = t->v[j];
@@ -322,7 +322,7 @@ static uint32_t iicp_sample(const oo_graph *g, const oo_table *t, uint32_t qid,
             ++Y;
         }
     }
-    /* Stage 2, lines 7-12: FIFO BFS over unvisited out-neighbours */
+    /* Stage 2: FIFO BFS over unvisited out-neighbours */
     while (head < tail) {
         int32_t u = w->queue[head++];
         int64_t b = g->row_ptr[u], e1 = g->row_ptr[u + 1];
@@ -476,7 +476,7 @@ typedef struct {
     int32_t early;      /* the (first) GSRA returned a without sampling */
 } oo_rsa_result;
 
-/* Upsilon of Alg. 2, line 2, with c(eps', delta) from Table 1 (R8). */
+/* Upsilon of Alg. 2, with c(eps', delta) from Table 1 (R8). */
 static double upsilon(double eps, double delta, double a, double b)
 {
     double L = log(2.0 / delta);
@@ -495,17 +495,17 @@ static void gsra(oo_next_fn next, void *ctx, double eps, double delta, double a,
                  double scale, double offset, double *mu, uint64_t *T_out, uint64_t *h_out,
                  double *ups_out, int32_t *early)
 {
-    if (b - a < eps * b) {           /* line 1 */
+    if (b - a < eps * b) {           /* the early exit of Alg. 2 */
         *mu = a; *T_out = 0; *h_out = 0; *ups_out = 0.0; *early = 1;
         return;
     }
-    double ups = upsilon(eps, delta, a, b);   /* line 2 */
-    uint64_t h = 0, T = 0;                    /* line 3 */
-    while (sumx(scale, offset, h, T) < ups) { /* lines 4-5 */
+    double ups = upsilon(eps, delta, a, b);   /* the threshold */
+    uint64_t h = 0, T = 0;
+    while (sumx(scale, offset, h, T) < ups) { /* draw until the sum reaches it */
         h += next(ctx, 0, T);
         ++T;
     }
-    *mu = sumx(scale, offset, h, T) / (double)T;   /* line 6, R9 */
+    *mu = sumx(scale, offset, h, T) / (double)T;   /* R9 */
     *T_out = T; *h_out = h; *ups_out = ups; *early = 0;
 }
 
@@ -516,16 +516,16 @@ int oo_rsa(oo_next_fn next, void *ctx, double eps, double delta, double a, doubl
     memset(r, 0, sizeof(*r));
     if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 0.5) || !(b > a) || !(a >= 0.0))
         return OO_EINVAL;
-    if (eps >= 0.25) {                                   /* lines 1-2 */
+    if (eps >= 0.25) {                                   /* Alg. 3 reduces to GSRA */
         r->gsra_only = 1;
         gsra(next, ctx, eps, delta, a, b, scale, offset, &r->mu, &r->T1, &r->h1, &r->ups1, &r->early);
         r->T = r->T1; r->hT = r->h1; r->drawn_x = r->T1;
         return OO_OK;
     }
     double se = sqrt(eps);
-    /* step 1, line 3 */
+    /* step 1 */
     gsra(next, ctx, se, delta / 3.0, a, b, scale, offset, &r->mu1, &r->T1, &r->h1, &r->ups1, &r->early);
-    /* step 2, lines 4-7 */
+    /* step 2 */
     double L = log(2.0 / delta);
     r->ups = upsilon(eps, delta, a, b);
     r->ups2 = 2.0 * (1.0 + se) / (1.0 - se) * (1.0 + log(1.5) / L) * r->ups;
@@ -544,7 +544,7 @@ int oo_rsa(oo_next_fn next, void *ctx, double eps, double delta, double a, doubl
     double rho1 = Delta / (double)r->nsigma;
     double rho2 = eps * r->mu1 * (b - a);
     double rho = rho1 > rho2 ? rho1 : rho2;
-    /* step 3, lines 8-10 */
+    /* step 3 */
     double tt = ceil(r->ups2 * rho / (r->mu1 * r->mu1 * (b - a)));
     if (!(tt < 4.0e18)) return OO_ERANGE;
     r->T = tt < 1.0 ? 1 : (uint64_t)tt;
@@ -642,8 +642,8 @@ int oo_estimate(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col
     }
     scratch_free(&c.w);
     if (rc == OO_OK) {
-        if (mode == 0) { *oi = t.beta0 * r->mu; *is = *oi + kd; }   /* Alg. 4 line 2 */
-        else { *is = r->mu; *oi = *is - kd; }                        /* Alg. 5 line 3 */
+        if (mode == 0) { *oi = t.beta0 * r->mu; *is = *oi + kd; }   /* Alg. 4's output */
+        else { *is = r->mu; *oi = *is - kd; }                        /* Alg. 5's output */
     }
     oo_table_free(&t);
     return rc;

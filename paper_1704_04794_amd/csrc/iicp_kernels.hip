@@ -109,7 +109,7 @@ __device__ __forceinline__ bool edge_live(uint32_t word, float p) {
   return p >= 1.0f || word < (uint32_t)(p * 4294967296.0f);
 }
 
-// Stage 1, line 2 of Alg. 1: t = U * beta_0, i = min{j : CDF_j > t}; if no
+// Alg. 1, Stage 1 selection: t = U * beta_0, i = min{j : CDF_j > t}; if no
 // entry qualifies, the last entry with Pr[A_j] > 0.
 __device__ int64_t select_entry(const QueryDev& Q, uint32_t seed, uint32_t stream, uint64_t s) {
   const Words d = philox_draw(Q.qid, seed, KIND_SELECT, stream, s, 0);
@@ -406,7 +406,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       if (pass_on) {
         st = T_IDLE;
       } else if (c_l == 1) {
-        // Stage 1 with a single table entry (lines 2-3 of Alg. 1 select it
+        // Stage 1 with a single table entry (the selection of Alg. 1 picks it
         // whatever U is, and no entry follows): v_0 is activated and, with
         // its row bounds read once per segment, popped at once, so the
         // sample examines its first edge group in this very iteration.
@@ -483,7 +483,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         }
       }
     } else if (st == T_START) {
-      // Stage 1, lines 2-3 of Alg. 1 (a single entry is selected whatever U is)
+      // Alg. 1, Stage 1: select and activate the first entry (a single entry is selected whatever U is)
       int64_t i = 0;
       if (ql > 1) {
         const QueryDev& Q = A.qs[A.segs[sg].q];
@@ -529,7 +529,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         st = T_POP;
       }
     } else if (st == T_STAGE1 || st == T_EXPAND) {
-      // Stage 1 lines 4-6 (table group) or Stage 2 lines 9-11 (edge group)
+      // Alg. 1: Stage-1 coins of a table group, or Stage-2 coins of an edge group
       uint32_t live = 0;
 #pragma unroll
       for (int b = 0; b < 4; ++b) {
@@ -773,7 +773,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
     }
     wave_sync();
     if (newmask) {
-      // lanes 0..K-1 start their slot's sample: Stage 1, lines 2-3 of Alg. 1
+      // lanes 0..K-1 start their slot's sample: the Stage-1 selection of Alg. 1
       if (lane < K && ((newmask >> lane) & 1u)) {
         const uint64_t f = W.s_f[lane];
         const uint32_t sg = find_segment(A, f);
@@ -1229,7 +1229,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
     }
     __syncthreads();
     const int64_t i = s_i;
-    // Stage 1, lines 4-6 of Alg. 1
+    // Alg. 1, Stage 1: one coin for each later table entry
     const int64_t gend = (Q.l + 3) >> 2;
     for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += NT) {
       const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
@@ -1244,7 +1244,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       }
     }
     __syncthreads();
-    // Stage 2, lines 7-12: expand the queue in batches of up to NT * LBN
+    // Alg. 1, Stage 2: expand the queue in batches of up to NT * LBN
     // nodes, LBN consecutive queue entries per thread (their row reads are
     // independent, so they are in flight together)
     uint32_t head = 0;

@@ -464,7 +464,7 @@ typedef unsigned __int128 u128;
 
 // Upsilon = (1 + eps) c(eps', delta) (b - a) with
 // eps' = eps (1 - eps b / ((2 + 2/3 eps) ln(2/delta) (b - a))) and
-// c(x, delta) = (2 + 2/3 x) ln(2/delta) / x^2 (Alg. 2 line 2, Table 1).
+// c(x, delta) = (2 + 2/3 x) ln(2/delta) / x^2 (Alg. 2, Table 1).
 double stop_threshold(double eps, double delta, double a, double b) {
   const double L = std::log(2.0 / delta);
   const double epsp = eps * (1.0 - (eps * b) / ((2.0 + (2.0 / 3.0) * eps) * L * (b - a)));
@@ -507,9 +507,9 @@ void finish_result(Rsa& R) {
   R.phase = P_DONE;
 }
 
-// Step 2 / step 3 set-up once step 1 has its estimate (Alg. 3 lines 4-9).
+// Step 2 / step 3 set-up once step 1 has its estimate (Alg. 3).
 oi_status after_step1(Rsa& R) {
-  if (R.gsra_only) {  // Alg. 3 lines 1-2: the GSRA estimate is the answer
+  if (R.gsra_only) {  // Alg. 3 with eps >= 1/4: the GSRA estimate is the answer
     R.r.T = R.r.T1;
     R.r.hT = R.r.h1;
     finish_result(R);
@@ -797,7 +797,7 @@ oi_status init_rsa(Rsa& R, HostQuery* Q, int64_t n, double eps, double delta, in
   R.r.gsra_only = R.gsra_only ? 1 : 0;
   R.e1 = R.gsra_only ? eps : std::sqrt(eps);
   R.d1 = R.gsra_only ? delta : delta / 3.0;
-  if (R.b - R.a < R.e1 * R.b) {  // Alg. 2 line 1
+  if (R.b - R.a < R.e1 * R.b) {  // the early exit of Alg. 2
     R.r.early = 1;
     R.r.T1 = 0;
     R.r.h1 = 0;
