@@ -217,7 +217,8 @@ typedef struct {
 /* Sampler-schedule autotuner (a tuning aid; results never depend on it).
  * Times one sampling launch of `pilot` samples (stream X, samples
  * 0..pilot-1) of up to four of the nq seed sets (spread over the list, those
- * with beta_0 = 0 skipped) under every combination of: the tiny kernel first
+ * with beta_0 = 0 skipped), best of two runs after an untimed one, under
+ * every combination of: the tiny kernel first
  * or not, each small-kernel variant, and automatic or always-direct routing
  * of hand-overs to the large kernel; then applies the fastest to the graph
  * (as oi_set_tuning / oi_set_routing would).  Seed sets are given as in

@@ -114,6 +114,16 @@ def test_cl1m_sigmoid_workload(P):
     g, sets, extra = make_config("cl1m_sig")
     S = sets[0]
     G = P.Graph.from_inputs(g)
+    # the forward of the full 1e6-sample estimate, sampled against the oracle
+    import torch
+    y, e, _ = G.sample_fixed(S, 1_000_000, want_e=True)
+    idx = np.unique(np.random.default_rng(5).integers(0, 1_000_000, 32))
+    sel = torch.from_numpy(idx).cuda()
+    yg = y[sel].cpu().numpy().view(np.uint32)
+    eg = e[sel].cpu().numpy().view(np.uint64)
+    for j, k in enumerate(idx):
+        o = O.sample_fixed(g, S, 0, RUN_SEED, 0, int(k), 1, want_e=True, nthreads=1)
+        assert int(o["y"][0]) == int(yg[j]) and int(o["e"][0]) == int(eg[j]), int(k)
     N = 200_000
     print(f"[gpu] backward cl1m_sig N={N}", flush=True)
     gg = _gpu_grad(P, G, S, N, param=P.OI_PARAM_P)

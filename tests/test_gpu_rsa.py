@@ -129,3 +129,31 @@ def test_autotune_keeps_results(P):
     for a, b in zip(before, after):
         assert a["oi"] == b["oi"] and a["T"] == b["T"] and a["samples_x"] == b["samples_x"]
     G.close()
+
+
+def test_cl1m_full_estimate_replayed_by_the_oracle(P):
+    """The 1M-node single-query workload at full size, in the configuration
+    the bench times (eps = 0.05, delta = 1e-6, SOIEA): the oracle draws the
+    same two streams itself (as many samples as the GPU's stopping indices
+    need) and replays RSA on them; every stopping index, sum and estimate
+    must agree.  The GPU's counts only size the oracle's arrays: a wrong
+    count leaves the oracle without the samples it needs or with a
+    different answer."""
+    g, sets, extra = make_config("cl1m")
+    S = sets[0]
+    G = P.Graph.from_inputs(g)
+    print("[gpu] rsa cl1m full size", flush=True)
+    a = G.estimate(S, extra["eps"], extra["delta"], mode=0, query_id=0)
+    G.close()
+    nx = max(a["T1"], a["T"]) + 4096
+    nxp = 2 * a["nsigma"]
+    print(f"[gpu] oracle draws {nx} + {nxp} samples", flush=True)
+    nt = O.nthreads_default()
+    x = O.sample_fixed(g, S, 0, RUN_SEED, 0, 0, nx, nthreads=nt)
+    xp = O.sample_fixed(g, S, 0, RUN_SEED, 1, 0, nxp, nthreads=nt)
+    b0 = x["beta0"]
+    r = O.rsa_arrays(x["y"], xp["y"], extra["eps"], extra["delta"], 1.0, float(g.n - len(S)))
+    del x, xp
+    for f in FIELDS:
+        assert a[f] == r[f], (f, a[f], r[f])
+    assert a["mu"] == r["mu"] and a["oi"] == b0 * r["mu"]
