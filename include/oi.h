@@ -202,6 +202,14 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
  * Changing large_qcap reallocates the pool.  Results do not depend on
  * either setting.  Errors: OI_EINVAL for a null graph or small_direct > 2. */
 oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
+/* Queued RSA rounds.  In steps 2 and 3 of the RSA estimator (Alg. 3) the
+ * number of samples is fixed when the step starts, so a round that neither
+ * starts nor ends a step determines the next one: with enable != 0 (the
+ * default) the next round is queued on the stream before this one's sums are
+ * read back, and the GPU does not wait for the host between them; 0 reads
+ * every round back before planning the next.  Results do not depend on it.
+ * Errors: OI_EINVAL for a null graph. */
+oi_status oi_set_pipeline(oi_graph* g, int enable);
 /* What oi_autotune chose and measured. */
 typedef struct {
   int32_t variant;      /* small-kernel variant */

@@ -13,7 +13,7 @@ from ._binding import (  # noqa: F401
     oi_gather_probe,
     oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
     oi_graph_set_theta, oi_last_error,
-    oi_num_variants, oi_sample_fixed, oi_set_routing, oi_set_stream, oi_set_tuning, oi_stage1_table, oi_timing_enable,
+    oi_num_variants, oi_sample_fixed, oi_set_pipeline, oi_set_routing, oi_set_stream, oi_set_tuning, oi_stage1_table, oi_timing_enable,
     oi_timing_get, oi_variant_info)
 
 RUN_SEED = 0x17044794
@@ -117,7 +117,10 @@ class Graph:
             oi_timing_enable(self.h, enable)
         return oi_timing_get(self.h)
 
-    def tune(self, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1, small_direct=-1, large_qcap=-1):
+    def tune(self, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1, small_direct=-1, large_qcap=-1,
+             pipeline=None):
         oi_set_tuning(self.h, variant, chunk, tiny, tiny_chunk, round_max)
         if small_direct >= 0 or large_qcap > 0:
             oi_set_routing(self.h, small_direct, large_qcap)
+        if pipeline is not None:
+            oi_set_pipeline(self.h, pipeline)

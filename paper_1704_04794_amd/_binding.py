@@ -93,6 +93,7 @@ def _load():
         "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
         "oi_gather_probe": [vp, u64, u32, P(u64), P(u64), P(dbl)],
         "oi_set_routing": [vp, ci, i64],
+        "oi_set_pipeline": [vp, ci],
         "oi_autotune": [vp, i32, vp, vp, vp, u64, u32, P(oi_autotune_result)],
     }
     for name, args in sig.items():
@@ -251,6 +252,10 @@ def oi_set_tuning(g, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1)
 
 def oi_set_routing(g, small_direct=-1, large_qcap=-1):
     _check("oi_set_routing", _lib.oi_set_routing(g, int(small_direct), int(large_qcap)))
+
+
+def oi_set_pipeline(g, enable):
+    _check("oi_set_pipeline", _lib.oi_set_pipeline(g, 1 if enable else 0))
 
 
 def oi_autotune(g, seed_off, seeds, query_ids, pilot, run_seed):

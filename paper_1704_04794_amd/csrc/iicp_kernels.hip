@@ -1187,6 +1187,9 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
   uint32_t* bits = A.bits + (int64_t)blockIdx.x * A.bits_words;
   int32_t* queue = A.queue + (int64_t)blockIdx.x * A.queue_stride;
   const uint32_t nd = *A.nlist2;
+  // a block past the list's length could never take a sample: it leaves
+  // without touching the shared counter (most launches have few or none)
+  if (blockIdx.x >= nd) return;
   while (true) {
     if (tid == 0) s_di = (uint32_t)atomicAdd(A.counter2, 1ull);
     __syncthreads();

@@ -96,9 +96,80 @@ struct DevBuf {
   }
 };
 
+// Page-locked host memory, so that copies to and from it run asynchronously
+// on the stream.
+struct PinBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  PinBuf() = default;
+  PinBuf(const PinBuf&) = delete;
+  PinBuf& operator=(const PinBuf&) = delete;
+  ~PinBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t ensure(size_t b) {
+    if (b == 0) b = 16;
+    if (bytes >= b) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc(&p, b, hipHostMallocDefault);
+    if (e == hipSuccess) bytes = b;
+    return e;
+  }
+  template <typename T>
+  T* as() const {
+    return static_cast<T*>(p);
+  }
+};
+
 constexpr uint32_t kChunk = 4096;        // Y values per chunk sum (stopping-rule bookkeeping)
 constexpr uint64_t kMaxSample = 1ull << 59;
 constexpr uint64_t kStep3Rounds = 2;     // a step-3-only round may hold this many round_max
+
+struct HostQuery;
+
+// One sampling request: `count` samples of stream `stream` from index
+// `first`, Y written at out_off of the round buffer.
+struct SegReq {
+  uint32_t q;
+  uint32_t stream;
+  uint64_t first;
+  uint64_t count;
+  uint64_t out_off;
+};
+
+enum Phase { P_DONE = 0, P_STEP1 = 1, P_STEP2 = 2, P_STEP3 = 3 };
+
+// An RSA round as it travels through the stream: its plan, the device copies
+// of its segment and query tables, and one result block
+//   ctl[16] | per segment (sum Y, sum E) | per pair segment D (lo, hi) | chunk sums
+// that is cleared before and copied to page-locked memory after the round.
+// Two slots let the next round be queued before this one is read back.
+struct RoundSlot {
+  DevBuf d_segs, d_qs, d_pairs, d_res;
+  PinBuf h_segs, h_qs, h_pairs, h_res;
+  hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // [6]: round done
+  std::vector<const HostQuery*> qv;
+  std::vector<SegReq> segs;
+  std::vector<int> seg_owner;
+  std::vector<Phase> seg_phase;
+  std::vector<size_t> pair_seg;  // segment of each pair accumulator
+  uint64_t total = 0, off = 0, nch = 0, ptotal = 0;
+  bool write_y = false, chunk_sums = false, giant_inline = false, timed = false;
+  RoundSlot() = default;
+  RoundSlot(const RoundSlot&) = delete;
+  RoundSlot& operator=(const RoundSlot&) = delete;
+  ~RoundSlot() {
+    for (hipEvent_t& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  size_t sums_at() const { return 16; }
+  size_t pacc_at() const { return 16 + 2 * segs.size(); }
+  size_t chunks_at() const { return 16 + 2 * segs.size() + 2 * pair_seg.size(); }
+  size_t words() const { return chunks_at() + nch; }
+};
 
 }  // namespace
 
@@ -112,7 +183,7 @@ struct oi_graph {
   std::vector<float> p;
   DevBuf d_row_ptr, d_eg;
   // per-launch workspaces
-  DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_chunks, d_pairs, d_pacc, d_bits, d_queue;
+  DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_bits, d_queue;
   int large_blocks = 0;
   uint32_t large_qcap = 0;          // queue entries per large-kernel block
   DevBuf d_gbits, d_gqueue;         // full-size pool for samples that outgrow large_qcap
@@ -124,6 +195,8 @@ struct oi_graph {
   uint32_t chunk = 256;
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
   uint64_t round_max = 1ull << 28;  // samples per launch: 1 GiB of Y, 2 GiB per hand-over list
+  RoundSlot slots[2];
+  bool pipeline = true;             // queue a round whose plan is known before the last is read back
   // timing
   bool timing = false;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -238,14 +311,6 @@ oi_status upload_query(oi_graph* g, HostQuery& Q) {
 // ---------------------------------------------------------------------------
 // sampling launches
 // ---------------------------------------------------------------------------
-struct SegReq {
-  uint32_t q;
-  uint32_t stream;
-  uint64_t first;
-  uint64_t count;
-  uint64_t out_off;
-};
-
 struct BwdBufs {
   const uint32_t* y_in = nullptr;
   unsigned long long *live = nullptr, *dead = nullptr, *tab = nullptr;
@@ -301,7 +366,121 @@ oi_status ensure_giant_pool(oi_graph* g) {
   return OI_OK;
 }
 
-// Runs the small- and large-cascade kernels over `segs`.  Y goes to y_dev
+// Launch arguments shared by every sampling launch.  ctl is the 16-word
+// control block:
+//   [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier
+//   sums, [11] counter2, [12] nlist3, [13] the full-queue pass's counter
+// and sums holds (sum Y, sum E) per segment.
+oi::SampleLaunch make_launch(const oi_graph* g, const oi::Segment* d_segs, const oi::QueryDev* d_qs, int32_t nseg,
+                             uint64_t total, uint32_t seed, uint32_t* y_dev, uint64_t* e_dev,
+                             unsigned long long* ctl, unsigned long long* sums) {
+  oi::SampleLaunch A{};
+  A.n = g->n;
+  A.row_ptr = g->d_row_ptr.as<int64_t>();
+  A.eg = g->d_eg.as<oi::EdgeGroup>();
+  A.qs = d_qs;
+  A.segs = d_segs;
+  A.nseg = nseg;
+  A.total = total;
+  A.seed = seed;
+  A.y_out = y_dev;
+  A.e_out = e_dev;
+  A.seg_sums = sums;
+  A.tier_sums = ctl + 5;
+  A.counter = ctl;
+  A.counter1 = ctl + 1;
+  A.counter2 = ctl + 11;
+  A.list1 = g->d_def.as<unsigned long long>();
+  A.nlist1 = reinterpret_cast<unsigned int*>(ctl + 2);
+  A.list2 = g->d_def2.as<unsigned long long>();
+  A.nlist2 = reinterpret_cast<unsigned int*>(ctl + 3);
+  A.small_from_list1 = g->use_tiny ? 1 : 0;
+  A.small_direct_max = g->small_direct == 1 ? 0xFFFFFFFFu : (g->small_direct == 2 ? 0u : (uint32_t)g->large_blocks);
+  A.err = reinterpret_cast<unsigned int*>(ctl + 4);
+  A.chunk = g->chunk;
+  A.tiny_chunk = g->tiny_chunk;
+  A.bits = g->d_bits.as<uint32_t>();
+  A.queue = g->d_queue.as<int32_t>();
+  A.bits_words = (g->n + 31) / 32;
+  A.qcap = g->large_qcap;
+  A.queue_stride = (int64_t)g->large_qcap;
+  // list1's storage is free once the small kernel has run: it holds list3
+  A.list3 = g->d_def.as<unsigned long long>();
+  A.nlist3 = reinterpret_cast<unsigned int*>(ctl + 12);
+  return A;
+}
+
+// The pass over list3 with n-entry queues (it cannot overflow).  Its blocks
+// leave at once when list3 is empty, so it may be queued unconditionally.
+oi::SampleLaunch make_giant_launch(const oi_graph* g, const oi::SampleLaunch& A, unsigned long long* ctl) {
+  oi::SampleLaunch B = A;
+  B.list2 = A.list3;
+  B.nlist2 = A.nlist3;
+  B.counter2 = ctl + 13;
+  B.bits = g->d_gbits.as<uint32_t>();
+  B.queue = g->d_gqueue.as<int32_t>();
+  B.qcap = (uint32_t)std::min<int64_t>(g->n, 0xFFFFFFFFll);
+  B.queue_stride = g->n;
+  B.list3 = nullptr;
+  B.nlist3 = nullptr;
+  return B;
+}
+
+// tiny -> small -> large kernels of one launch over A.total samples; ev
+// (four events, or null) brackets the three.
+oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t* ev) {
+  const uint64_t want_waves = (A.total + 63) / 64;
+  int bpc = 0;
+  if (ev) HIP_TRY(hipEventRecord(ev[0], g->stream));
+  if (g->use_tiny) {
+    HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
+    if (bpc < 1) bpc = 1;
+    const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
+    if (g->tiny_chunk == 0) {
+      const uint64_t c = A.total / ((uint64_t)blocks * 4 * 8);
+      A.tiny_chunk = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(256, c));
+    }
+    HIP_TRY(oi::launch_tiny(is_bwd, A, blocks, g->stream));
+  }
+  if (ev) HIP_TRY(hipEventRecord(ev[1], g->stream));
+  HIP_TRY(oi::small_occupancy(g->variant, is_bwd, &bpc));
+  if (bpc < 1) bpc = 1;
+  {
+    // the small kernel sees only what the tiny kernel handed over; its grid
+    // must not depend on that count (it is on the device), so it is sized
+    // for the whole launch and idle waves exit at once
+    const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
+    HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, g->stream));
+  }
+  if (ev) HIP_TRY(hipEventRecord(ev[2], g->stream));
+  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
+  if (ev) HIP_TRY(hipEventRecord(ev[3], g->stream));
+  return OI_OK;
+}
+
+void add_timing(oi_graph* g, const unsigned long long* hctl, uint64_t total, float tiny_ms, float small_ms,
+                float large_ms) {
+  g->tm.tiny_ms += tiny_ms;
+  g->tm.small_ms += small_ms;
+  g->tm.large_ms += large_ms;
+  g->tm.launches += 1;
+  g->tm.samples += total;
+  g->tm.handed_small += hctl[2] & 0xffffffffull;
+  g->tm.handed_large += hctl[3] & 0xffffffffull;
+  g->tm.tiny_y += hctl[5];
+  g->tm.tiny_edges += hctl[6];
+  g->tm.small_y += hctl[7];
+  g->tm.small_edges += hctl[8];
+  g->tm.large_y += hctl[9];
+  g->tm.large_edges += hctl[10];
+}
+
+oi_status elapsed(hipEvent_t a, hipEvent_t b, float* ms) {
+  HIP_TRY(hipEventElapsedTime(ms, a, b));
+  return OI_OK;
+}
+
+// Runs the sampling kernels over `segs` and waits for them.  Y goes to y_dev
 // (indexed by out_off) unless bwd; per-segment sums come back in sums.
 oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, const std::vector<SegReq>& segs,
                       uint32_t seed, uint32_t* y_dev, uint64_t* e_dev, std::vector<unsigned long long>& sums,
@@ -335,42 +514,9 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   HIP_TRY(hipMemsetAsync(g->d_sums.p, 0, sums.size() * sizeof(unsigned long long), g->stream));
   HIP_TRY(hipMemsetAsync(g->d_ctl.p, 0, 16 * sizeof(unsigned long long), g->stream));
 
-  // control block: [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier sums,
-  // [11] counter2, [12] nlist3, [13] the second large pass's counter
   unsigned long long* ctl = g->d_ctl.as<unsigned long long>();
-  oi::SampleLaunch A{};
-  A.n = g->n;
-  A.row_ptr = g->d_row_ptr.as<int64_t>();
-  A.eg = g->d_eg.as<oi::EdgeGroup>();
-  A.qs = g->d_qs.as<oi::QueryDev>();
-  A.segs = g->d_segs.as<oi::Segment>();
-  A.nseg = (int32_t)ds.size();
-  A.total = total;
-  A.seed = seed;
-  A.y_out = y_dev;
-  A.e_out = e_dev;
-  A.seg_sums = g->d_sums.as<unsigned long long>();
-  A.tier_sums = ctl + 5;
-  A.counter = ctl;
-  A.counter1 = ctl + 1;
-  A.counter2 = ctl + 11;
-  A.list1 = g->d_def.as<unsigned long long>();
-  A.nlist1 = reinterpret_cast<unsigned int*>(ctl + 2);
-  A.list2 = g->d_def2.as<unsigned long long>();
-  A.nlist2 = reinterpret_cast<unsigned int*>(ctl + 3);
-  A.small_from_list1 = g->use_tiny ? 1 : 0;
-  A.small_direct_max = g->small_direct == 1 ? 0xFFFFFFFFu : (g->small_direct == 2 ? 0u : (uint32_t)g->large_blocks);
-  A.err = reinterpret_cast<unsigned int*>(ctl + 4);
-  A.chunk = g->chunk;
-  A.tiny_chunk = g->tiny_chunk;
-  A.bits = g->d_bits.as<uint32_t>();
-  A.queue = g->d_queue.as<int32_t>();
-  A.bits_words = (g->n + 31) / 32;
-  A.qcap = g->large_qcap;
-  A.queue_stride = (int64_t)g->large_qcap;
-  // list1's storage is free once the small kernel has run: it holds list3
-  A.list3 = g->d_def.as<unsigned long long>();
-  A.nlist3 = reinterpret_cast<unsigned int*>(ctl + 12);
+  oi::SampleLaunch A = make_launch(g, g->d_segs.as<oi::Segment>(), g->d_qs.as<oi::QueryDev>(), (int32_t)ds.size(),
+                                   total, seed, y_dev, e_dev, ctl, g->d_sums.as<unsigned long long>());
   const bool is_bwd = bwd != nullptr;
   if (is_bwd) {
     A.y_in = bwd->y_in;
@@ -378,56 +524,22 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     A.acc_dead = bwd->dead;
     A.acc_tab = bwd->tab;
   }
-  const uint64_t want_waves = (total + 63) / 64;
-  int bpc = 0;
-  if (g->timing) HIP_TRY(hipEventRecord(g->ev[0], g->stream));
-  if (g->use_tiny) {
-    HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
-    if (bpc < 1) bpc = 1;
-    const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
-    if (g->tiny_chunk == 0) {
-      const uint64_t c = total / ((uint64_t)blocks * 4 * 8);
-      A.tiny_chunk = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(256, c));
-    }
-    HIP_TRY(oi::launch_tiny(is_bwd, A, blocks, g->stream));
-  }
-  if (g->timing) HIP_TRY(hipEventRecord(g->ev[1], g->stream));
-  HIP_TRY(oi::small_occupancy(g->variant, is_bwd, &bpc));
-  if (bpc < 1) bpc = 1;
-  {
-    // the small kernel sees only what the tiny kernel handed over; its grid
-    // must not depend on that count (it is on the device), so it is sized
-    // for the whole launch and idle waves exit at once
-    const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
-    HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, g->stream));
-  }
-  if (g->timing) HIP_TRY(hipEventRecord(g->ev[2], g->stream));
-  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
-  if (g->timing) HIP_TRY(hipEventRecord(g->ev[3], g->stream));
+  OI_TRY(launch_tiers(g, A, is_bwd, g->timing ? g->ev : nullptr));
   unsigned long long hctl[16] = {0};
   HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
   float giant_ms = 0.f;
   if ((hctl[12] & 0xffffffffull) != 0 && (hctl[4] & 0xffffffffull) == 0) {
     // samples that outgrew the main pool's queues: one more pass of the
-    // large kernel over list3 with n-entry queues (it cannot overflow)
+    // large kernel over list3 with n-entry queues
     OI_TRY(ensure_giant_pool(g));
-    oi::SampleLaunch B = A;
-    B.list2 = A.list3;
-    B.nlist2 = A.nlist3;
-    B.counter2 = ctl + 13;
-    B.bits = g->d_gbits.as<uint32_t>();
-    B.queue = g->d_gqueue.as<int32_t>();
-    B.qcap = (uint32_t)std::min<int64_t>(g->n, 0xFFFFFFFFll);
-    B.queue_stride = g->n;
-    B.list3 = nullptr;
-    B.nlist3 = nullptr;
+    const oi::SampleLaunch B = make_giant_launch(g, A, ctl);
     if (g->timing) HIP_TRY(hipEventRecord(g->ev[4], g->stream));
     HIP_TRY(oi::launch_large_full(is_bwd, B, g->giant_blocks, g->stream));
     if (g->timing) HIP_TRY(hipEventRecord(g->ev[5], g->stream));
     HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
-    if (g->timing) HIP_TRY(hipEventElapsedTime(&giant_ms, g->ev[4], g->ev[5]));
+    if (g->timing) OI_TRY(elapsed(g->ev[4], g->ev[5], &giant_ms));
   }
   HIP_TRY(hipMemcpyAsync(sums.data(), g->d_sums.p, sums.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                          g->stream));
@@ -437,22 +549,10 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   if (rounds) ++*rounds;
   if (g->timing) {
     float t0 = 0, t1 = 0, t2 = 0;
-    HIP_TRY(hipEventElapsedTime(&t0, g->ev[0], g->ev[1]));
-    HIP_TRY(hipEventElapsedTime(&t1, g->ev[1], g->ev[2]));
-    HIP_TRY(hipEventElapsedTime(&t2, g->ev[2], g->ev[3]));
-    g->tm.tiny_ms += t0;
-    g->tm.small_ms += t1;
-    g->tm.large_ms += t2 + giant_ms;
-    g->tm.launches += 1;
-    g->tm.samples += total;
-    g->tm.handed_small += hctl[2] & 0xffffffffull;
-    g->tm.handed_large += hctl[3] & 0xffffffffull;
-    g->tm.tiny_y += hctl[5];
-    g->tm.tiny_edges += hctl[6];
-    g->tm.small_y += hctl[7];
-    g->tm.small_edges += hctl[8];
-    g->tm.large_y += hctl[9];
-    g->tm.large_edges += hctl[10];
+    OI_TRY(elapsed(g->ev[0], g->ev[1], &t0));
+    OI_TRY(elapsed(g->ev[1], g->ev[2], &t1));
+    OI_TRY(elapsed(g->ev[2], g->ev[3], &t2));
+    add_timing(g, hctl, total, t0, t1, t2 + giant_ms);
   }
   return OI_OK;
 }
@@ -471,8 +571,6 @@ double stop_threshold(double eps, double delta, double a, double b) {
   const double c = (2.0 + (2.0 / 3.0) * epsp) * L / (epsp * epsp);
   return (1.0 + eps) * c * (b - a);
 }
-
-enum Phase { P_DONE = 0, P_STEP1 = 1, P_STEP2 = 2, P_STEP3 = 3 };
 
 struct Rsa {
   HostQuery* Q = nullptr;
@@ -597,13 +695,189 @@ oi_status scan_crossing(oi_graph* g, Rsa& R, const std::vector<unsigned long lon
 
 uint64_t round_up(uint64_t x, uint64_t m) { return (x + m - 1) / m * m; }
 
+// Queue one RSA round, whose plan is in S, on the stream: the segment and
+// query tables, the sampling kernels, the full-queue pass when its pool
+// exists, the chunk sums of a round that writes Y, the paired squared
+// differences of X' segments, and the copy of the result block to S.h_res.
+oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
+  const size_t ns = S.segs.size();
+  HIP_TRY(S.h_segs.ensure(ns * sizeof(oi::Segment)));
+  HIP_TRY(S.h_qs.ensure(S.qv.size() * sizeof(oi::QueryDev)));
+  oi::Segment* ds = S.h_segs.as<oi::Segment>();
+  uint64_t total = 0;
+  for (size_t i = 0; i < ns; ++i) {
+    const SegReq& r = S.segs[i];
+    if (r.first + r.count > kMaxSample) return fail(OI_ERANGE, "sample index beyond 2^59");
+    ds[i].q = r.q;
+    ds[i].stream = r.stream;
+    ds[i].first = r.first;
+    ds[i].count = r.count;
+    ds[i].out_off = r.out_off;
+    ds[i].flat0 = total;
+    total += r.count;
+  }
+  if (total == 0) return fail(OI_ESTATE, "empty round");
+  if (total > (1ull << 32)) return fail(OI_ERANGE, "too many samples in one launch");
+  S.total = total;
+  oi::QueryDev* qd = S.h_qs.as<oi::QueryDev>();
+  for (size_t i = 0; i < S.qv.size(); ++i) qd[i] = S.qv[i]->dev;
+  // X' segments: one 128-bit accumulator each for sum (Y'_{2i-1} - Y'_{2i})^2
+  struct PairDesc {
+    uint64_t out_off, npairs, flat0;
+    uint32_t acc, pad;
+  };
+  static_assert(sizeof(PairDesc) == 32, "PairSeg layout");
+  if (oi::pair_seg_size() != sizeof(PairDesc)) return fail(OI_ESTATE, "PairSeg layout mismatch");
+  S.pair_seg.clear();
+  S.ptotal = 0;
+  for (size_t i = 0; i < ns; ++i)
+    if (S.segs[i].stream == 1) S.pair_seg.push_back(i);
+  HIP_TRY(S.h_pairs.ensure(S.pair_seg.size() * sizeof(PairDesc)));
+  PairDesc* pd = S.h_pairs.as<PairDesc>();
+  for (size_t j = 0; j < S.pair_seg.size(); ++j) {
+    const SegReq& r = S.segs[S.pair_seg[j]];
+    pd[j] = PairDesc{r.out_off, r.count / 2, S.ptotal, (uint32_t)j, 0u};
+    S.ptotal += r.count / 2;
+  }
+  if (S.ptotal && !S.write_y) return fail(OI_ESTATE, "paired differences need Y");
+  S.nch = S.chunk_sums ? (S.off + kChunk - 1) / kChunk : 0;
+  OI_TRY(ensure_large_pool(g));
+  S.giant_inline = S.giant_inline || g->giant_blocks > 0;
+  if (!S.ev[0]) {
+    for (int i = 0; i < 6; ++i) HIP_TRY(hipEventCreate(&S.ev[i]));
+    HIP_TRY(hipEventCreateWithFlags(&S.ev[6], hipEventDisableTiming));
+  }
+  const size_t words = S.words();
+  HIP_TRY(S.h_res.ensure(words * 8));
+  HIP_TRY(S.d_segs.ensure(ns * sizeof(oi::Segment)));
+  HIP_TRY(S.d_qs.ensure(S.qv.size() * sizeof(oi::QueryDev)));
+  HIP_TRY(S.d_pairs.ensure(S.pair_seg.size() * sizeof(PairDesc)));
+  HIP_TRY(S.d_res.ensure(words * 8));
+  // the hand-over lists are shared by the queued rounds: growing them waits
+  // for the round in flight
+  if (g->d_def.bytes < total * sizeof(unsigned long long) || g->d_def2.bytes < total * sizeof(unsigned long long))
+    HIP_TRY(hipStreamSynchronize(g->stream));
+  HIP_TRY(g->d_def.ensure(total * sizeof(unsigned long long)));
+  HIP_TRY(g->d_def2.ensure(total * sizeof(unsigned long long)));
+  HIP_TRY(hipMemcpyAsync(S.d_segs.p, ds, ns * sizeof(oi::Segment), hipMemcpyHostToDevice, g->stream));
+  HIP_TRY(hipMemcpyAsync(S.d_qs.p, qd, S.qv.size() * sizeof(oi::QueryDev), hipMemcpyHostToDevice, g->stream));
+  if (!S.pair_seg.empty())
+    HIP_TRY(hipMemcpyAsync(S.d_pairs.p, pd, S.pair_seg.size() * sizeof(PairDesc), hipMemcpyHostToDevice, g->stream));
+  unsigned long long* res = S.d_res.as<unsigned long long>();
+  HIP_TRY(hipMemsetAsync(res, 0, S.chunks_at() * 8, g->stream));
+  uint32_t* ydev = g->d_y.as<uint32_t>();
+  oi::SampleLaunch A = make_launch(g, S.d_segs.as<oi::Segment>(), S.d_qs.as<oi::QueryDev>(), (int32_t)ns, total,
+                                   seed, S.write_y ? ydev : nullptr, nullptr, res, res + S.sums_at());
+  S.timed = g->timing;
+  OI_TRY(launch_tiers(g, A, false, S.timed ? S.ev : nullptr));
+  if (S.giant_inline) {
+    const oi::SampleLaunch B = make_giant_launch(g, A, res);
+    if (S.timed) HIP_TRY(hipEventRecord(S.ev[4], g->stream));
+    HIP_TRY(oi::launch_large_full(false, B, g->giant_blocks, g->stream));
+    if (S.timed) HIP_TRY(hipEventRecord(S.ev[5], g->stream));
+  }
+  if (S.nch) HIP_TRY(oi::launch_chunk_sums(ydev, S.off, kChunk, res + S.chunks_at(), g->stream));
+  if (S.ptotal)
+    HIP_TRY(oi::launch_pair_sq(ydev, S.d_pairs.p, (int32_t)S.pair_seg.size(), S.ptotal, res + S.pacc_at(),
+                               g->stream));
+  HIP_TRY(hipMemcpyAsync(S.h_res.p, res, words * 8, hipMemcpyDeviceToHost, g->stream));
+  HIP_TRY(hipEventRecord(S.ev[6], g->stream));
+  return OI_OK;
+}
+
+// Wait for a queued round's result block.  A round queued without the
+// full-queue pass in which a sample outgrew the main pool is run again with
+// that pass (it draws the same samples); such a round is never followed by
+// another queued one, so the round buffer is still its own.
+oi_status wait_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
+  HIP_TRY(hipEventSynchronize(S.ev[6]));
+  const unsigned long long* res = S.h_res.as<unsigned long long>();
+  if ((res[4] & 0xffffffffull) == 0 && (res[12] & 0xffffffffull) != 0 && !S.giant_inline) {
+    OI_TRY(ensure_giant_pool(g));
+    S.giant_inline = true;
+    OI_TRY(enqueue_round(g, S, seed));
+    HIP_TRY(hipEventSynchronize(S.ev[6]));
+    res = S.h_res.as<unsigned long long>();
+  }
+  const unsigned int err = (unsigned int)(res[4] & 0xffffffffull);
+  if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
+  if (S.timed) {
+    float t0 = 0, t1 = 0, t2 = 0, t3 = 0;
+    OI_TRY(elapsed(S.ev[0], S.ev[1], &t0));
+    OI_TRY(elapsed(S.ev[1], S.ev[2], &t1));
+    OI_TRY(elapsed(S.ev[2], S.ev[3], &t2));
+    if (S.giant_inline) OI_TRY(elapsed(S.ev[4], S.ev[5], &t3));
+    add_timing(g, res, S.total, t0, t1, t2 + t3);
+  }
+  return OI_OK;
+}
+
+// Fold a finished round into the RSA states.  Step-2 pair counts and step-3
+// sample counts were advanced when the round was queued; the phase ends are
+// taken from the segment's own range, since later rounds may be queued.
+oi_status absorb_round(oi_graph* g, std::vector<Rsa>& rs, RoundSlot& S, uint32_t seed) {
+  const unsigned long long* res = S.h_res.as<unsigned long long>();
+  const unsigned long long* sums = res + S.sums_at();
+  const unsigned long long* pacc = res + S.pacc_at();
+  const unsigned long long* ch = res + S.chunks_at();
+  uint32_t* ydev = g->d_y.as<uint32_t>();
+  size_t pj = 0;
+  for (size_t i = 0; i < S.segs.size(); ++i) {
+    Rsa& R = rs[S.seg_owner[i]];
+    const SegReq& sq = S.segs[i];
+    R.r.rounds += 1;
+    R.r.sum_y += sums[2 * i];
+    R.r.edges_examined += sums[2 * i + 1];
+    if (S.seg_phase[i] == P_STEP2) {
+      R.D += ((u128)pacc[2 * pj + 1] << 64) | (u128)pacc[2 * pj];
+      ++pj;
+      if (sq.first / 2 + sq.count / 2 == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
+    } else if (S.seg_phase[i] == P_STEP1) {
+      const uint64_t c0 = sq.out_off / kChunk, nc = (sq.count + kChunk - 1) / kChunk;
+      if (c0 + nc > S.nch) return fail(OI_ESTATE, "step-1 segment without chunk sums");
+      const std::vector<unsigned long long> mine(ch + c0, ch + c0 + nc);
+      bool found = false;
+      OI_TRY(scan_crossing(g, R, mine, R.nx, sq.count, ydev + sq.out_off, &found));
+      R.xchunks.insert(R.xchunks.end(), mine.begin(), mine.end());
+      R.nx += sq.count;
+      R.hx += sums[2 * i];
+      R.r.samples_x += sq.count;
+      if (found) {
+        OI_TRY(after_step1(R));
+        if (R.phase == P_STEP2 && R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
+      }
+    } else {  // step 3 extends stream X up to T (its chunk sums are never needed)
+      R.hx += sums[2 * i];
+      if (sq.first + sq.count == R.r.T) {
+        R.r.hT = R.hx;
+        finish_result(R);
+      }
+    }
+  }
+  return OI_OK;
+}
+
 // Drive every query in `rs` to completion.  Each round makes one sampling
 // launch that serves all unfinished queries; segments start at multiples of
 // kChunk in the round buffer so one chunk-sum launch covers all of them.
-oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
+// The plan of a round depends only on the queries' phases and counts; when
+// no query starts or ends a phase in a round (steps 2 and 3 run for a
+// number of samples fixed at their start), the next round is planned and
+// queued before this one is read back, so the GPU does not wait for the host
+// between them.
+oi_status rsa_drive_rounds(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
   HIP_TRY(g->d_y.ensure((size_t)g->round_max * 4));
+  int head = 0, inflight = 0;
+  auto retire = [&]() -> oi_status {
+    RoundSlot& S = g->slots[head];
+    OI_TRY(wait_round(g, S, seed));
+    head ^= 1;
+    --inflight;
+    return absorb_round(g, rs, S, seed);
+  };
   for (int guard = 0;; ++guard) {
     if (guard > 10000000) return fail(OI_ESTATE, "stopping rule did not converge");
+    if (inflight == 2) OI_TRY(retire());
     // Step 3 needs only the sum of X_1..X_T, no per-sample Y: a round whose
     // queries are all in step 3 writes no Y and may be kStep3Rounds times
     // larger (fewer launches and host round trips)
@@ -630,17 +904,25 @@ oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
         need = R.r.T - R.nx;
         if (need > cap) need = cap;
       }
+      if (need == 0) continue;
       want.push_back(need);
       owner.push_back((int)i);
     }
-    if (owner.empty()) break;
+    if (owner.empty()) {
+      if (inflight == 0) break;
+      while (inflight) OI_TRY(retire());
+      continue;
+    }
+    RoundSlot& S = g->slots[(head + inflight) & 1];
+    S.qv.clear();
+    S.segs.clear();
+    S.seg_owner.clear();
+    S.seg_phase.clear();
     // share the round buffer: at most an equal share each, whole chunks
     // (pairs for X'), and never past the end of the buffer
     const uint64_t share = std::max<uint64_t>(kChunk, cap / owner.size() / kChunk * kChunk);
-    std::vector<const HostQuery*> qv;
-    std::vector<SegReq> segs;
-    std::vector<int> seg_owner;
     uint64_t off = 0;
+    bool any_x = false;
     for (size_t j = 0; j < owner.size(); ++j) {
       Rsa& R = rs[owner[j]];
       uint64_t w = want[j];
@@ -652,104 +934,54 @@ oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
         if (w == 0) break;
       }
       SegReq sreq{};
-      sreq.q = (uint32_t)qv.size();
+      sreq.q = (uint32_t)S.qv.size();
       sreq.stream = R.phase == P_STEP2 ? 1u : 0u;
       sreq.first = R.phase == P_STEP2 ? 2 * R.pairs_done : R.nx;
       sreq.count = w;
       sreq.out_off = off;
-      qv.push_back(R.Q);
-      segs.push_back(sreq);
-      seg_owner.push_back(owner[j]);
+      any_x |= R.phase == P_STEP1;
+      S.qv.push_back(R.Q);
+      S.segs.push_back(sreq);
+      S.seg_owner.push_back(owner[j]);
+      S.seg_phase.push_back(R.phase);
       off = round_up(off + w, kChunk);
     }
-    std::vector<unsigned long long> sums;
-    int launches = 0;
-    OI_TRY(run_sampler(g, qv, segs, seed, all3 ? nullptr : g->d_y.as<uint32_t>(), nullptr, sums, nullptr,
-                       &launches));
-    uint32_t* ydev = g->d_y.as<uint32_t>();
-    // chunk sums over the whole round buffer (used by X segments)
-    bool any_x = false;
-    for (const SegReq& sq : segs) any_x |= sq.stream == 0;
-    any_x &= !all3;
-    std::vector<unsigned long long> ch;
-    if (any_x) {
-      const uint64_t nch = (off + kChunk - 1) / kChunk;
-      HIP_TRY(g->d_chunks.ensure(nch * 8));
-      HIP_TRY(oi::launch_chunk_sums(ydev, off, kChunk, g->d_chunks.as<unsigned long long>(), g->stream));
-      ch.resize(nch);
-      HIP_TRY(hipMemcpyAsync(ch.data(), g->d_chunks.p, nch * 8, hipMemcpyDeviceToHost, g->stream));
-    }
-    // squared paired differences for X' segments
-    std::vector<unsigned char> pbuf;
-    std::vector<size_t> pair_seg;
-    uint64_t ptotal = 0;
-    for (size_t i = 0; i < segs.size(); ++i) {
-      if (segs[i].stream != 1) continue;
-      struct {
-        uint64_t out_off, npairs, flat0;
-        uint32_t acc, pad;
-      } ps{segs[i].out_off, segs[i].count / 2, ptotal, (uint32_t)pair_seg.size(), 0};
-      static_assert(sizeof(ps) == 32, "PairSeg layout");
-      if (oi::pair_seg_size() != sizeof(ps)) return fail(OI_ESTATE, "PairSeg layout mismatch");
-      const unsigned char* pb = reinterpret_cast<const unsigned char*>(&ps);
-      pbuf.insert(pbuf.end(), pb, pb + sizeof(ps));
-      ptotal += segs[i].count / 2;
-      pair_seg.push_back(i);
-    }
-    std::vector<unsigned long long> pacc(2 * pair_seg.size());
-    if (!pair_seg.empty()) {
-      HIP_TRY(g->d_pairs.ensure(pbuf.size()));
-      HIP_TRY(g->d_pacc.ensure(pacc.size() * 8));
-      HIP_TRY(hipMemcpyAsync(g->d_pairs.p, pbuf.data(), pbuf.size(), hipMemcpyHostToDevice, g->stream));
-      HIP_TRY(hipMemsetAsync(g->d_pacc.p, 0, pacc.size() * 8, g->stream));
-      HIP_TRY(oi::launch_pair_sq(ydev, g->d_pairs.p, (int32_t)pair_seg.size(), ptotal,
-                                 g->d_pacc.as<unsigned long long>(), g->stream));
-      HIP_TRY(hipMemcpyAsync(pacc.data(), g->d_pacc.p, pacc.size() * 8, hipMemcpyDeviceToHost, g->stream));
-    }
-    HIP_TRY(hipStreamSynchronize(g->stream));
-    size_t pj = 0;
-    for (size_t i = 0; i < segs.size(); ++i) {
-      Rsa& R = rs[seg_owner[i]];
-      const SegReq& sq = segs[i];
-      R.r.rounds += 1;
-      R.r.sum_y += sums[2 * i];
-      R.r.edges_examined += sums[2 * i + 1];
-      if (sq.stream == 1) {
-        R.D += ((u128)pacc[2 * pj + 1] << 64) | (u128)pacc[2 * pj];
-        ++pj;
-        R.pairs_done += sq.count / 2;
-        R.r.samples_xp += sq.count;
-        if (R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
-        continue;
-      }
-      std::vector<unsigned long long> mine;
-      if (!all3) {
-        const uint64_t c0 = sq.out_off / kChunk, nc = (sq.count + kChunk - 1) / kChunk;
-        mine.assign(ch.begin() + (long)c0, ch.begin() + (long)(c0 + nc));
-      }
-      if (R.phase == P_STEP1) {
-        bool found = false;
-        OI_TRY(scan_crossing(g, R, mine, R.nx, sq.count, ydev + sq.out_off, &found));
-        R.xchunks.insert(R.xchunks.end(), mine.begin(), mine.end());
-        R.nx += sq.count;
-        R.hx += sums[2 * i];
-        R.r.samples_x += sq.count;
-        if (found) {
-          OI_TRY(after_step1(R));
-          if (R.phase == P_STEP2 && R.pairs_done == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
-        }
-      } else {  // step 3 extends stream X up to T (its chunk sums are never needed)
-        R.nx += sq.count;
-        R.hx += sums[2 * i];
-        R.r.samples_x += sq.count;
-        if (R.nx == R.r.T) {
-          R.r.hT = R.hx;
-          finish_result(R);
-        }
+    S.off = off;
+    S.write_y = !all3;
+    S.chunk_sums = any_x;
+    S.giant_inline = false;
+    OI_TRY(enqueue_round(g, S, seed));
+    ++inflight;
+    // advance the counts the plan fixes; a round that starts or ends a
+    // phase is read back before anything else is planned
+    const bool can_queue = g->pipeline && (S.giant_inline || (int64_t)g->large_qcap >= g->n);
+    bool ends = !can_queue;
+    for (size_t i = 0; i < S.segs.size(); ++i) {
+      Rsa& R = rs[S.seg_owner[i]];
+      if (S.seg_phase[i] == P_STEP2) {
+        R.pairs_done += S.segs[i].count / 2;
+        R.r.samples_xp += S.segs[i].count;
+        ends |= R.pairs_done == R.r.nsigma;
+      } else if (S.seg_phase[i] == P_STEP3) {
+        R.nx += S.segs[i].count;
+        R.r.samples_x += S.segs[i].count;
+        ends |= R.nx == R.r.T;
+      } else {
+        ends = true;
       }
     }
+    if (ends)
+      while (inflight) OI_TRY(retire());
   }
   return OI_OK;
+}
+
+oi_status rsa_drive(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
+  const oi_status st = rsa_drive_rounds(g, rs, seed);
+  // on an error, rounds may still be queued: let them finish before their
+  // buffers can be reused or freed
+  if (st != OI_OK) (void)hipStreamSynchronize(g->stream);
+  return st;
 }
 
 oi_status init_rsa(Rsa& R, HostQuery* Q, int64_t n, double eps, double delta, int mode) {
@@ -1257,6 +1489,12 @@ oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap) {
     g->d_queue.release();
     g->large_blocks = 0;
   }
+  return OI_OK;
+}
+
+oi_status oi_set_pipeline(oi_graph* g, int enable) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  g->pipeline = enable != 0;
   return OI_OK;
 }
 

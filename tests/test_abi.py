@@ -81,6 +81,7 @@ def test_null_handles_are_rejected():
                  lambda: P.oi_timing_get(None),
                  lambda: P.oi_set_tuning(None, 0),
                  lambda: P.oi_set_routing(None, 0),
+                 lambda: P.oi_set_pipeline(None, 1),
                  lambda: P.oi_autotune(None, np.array([0, 1], np.int64), np.array([0], np.int32),
                                        np.array([0], np.uint32), 4096, 1)):
         with pytest.raises(P.OiError) as ei:

@@ -65,6 +65,34 @@ def test_rsa_small_rounds_same_answer(P):
     G.close()
 
 
+def test_queued_rounds_same_answer(P):
+    """Rounds queued before the previous one is read back (steps 2 and 3)
+    give exactly the results of rounds read back one at a time, also when a
+    sample outgrows the large kernel's queues and its round is run again
+    with the full-size pass."""
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gw = g.with_p(wc_probs(g))
+    rng = np.random.default_rng(11)
+    sets = [uniform_seed_set(gw, int(k), int(s)) for k, s in zip(rng.integers(1, 30, 5), rng.integers(0, 1 << 30, 5))]
+    keys = FIELDS + ("oi", "is_", "mu", "mu1", "samples_x", "samples_xp", "rounds", "sum_y", "edges_examined")
+    for qcap in (-1, 24):
+        res = {}
+        for pipe in (False, True):
+            print(f"[gpu] queued rounds pipeline={pipe} large_qcap={qcap}", flush=True)
+            G = P.Graph.from_inputs(gw)
+            G.tune(round_max=16384, large_qcap=qcap, pipeline=pipe)
+            res[pipe] = (G.estimate_batch(sets, 0.2, 1e-2, mode=0, query_ids=np.arange(5, dtype=np.uint32)),
+                         [G.estimate(sets[0], 0.1, 1e-2, mode=1, query_id=9)])
+            G.close()
+        for a_list, b_list in zip(res[False], res[True]):
+            for a, b in zip(a_list, b_list):
+                for f in keys:
+                    assert a[f] == b[f], (qcap, f, a[f], b[f])
+        assert res[True][1][0]["rounds"] > 4
+    b = O.estimate(gw, sets[0], 0.1, 1e-2, 1, 9, RUN_SEED)
+    assert res[True][1][0]["oi"] == b["oi"] and res[True][1][0]["T"] == b["rsa"]["T"]
+
+
 def test_rsa_chung_lu(P):
     g = chung_lu_graph(20000, 200000, 2.1, 7)
     gt = g.with_p(trivalency_probs(g, 5))
