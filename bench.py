@@ -266,6 +266,8 @@ def main():
     ap.add_argument("--no-backward", action="store_true", help="skip the backward/forward ratio")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--variant", type=int, default=-1)
+    ap.add_argument("--pipeline", type=int, choices=(0, 1, 2), default=None,
+                    help="RSA rounds: 0 read back one at a time, 1 queued (default), 2 queued, one graph each")
     ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m"), default="cl1m",
                     help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time; "
                          "cl100m: the billion-edge graph")
@@ -309,6 +311,8 @@ def main():
     G = P.Graph.from_inputs(g)
     if args.variant >= 0:
         G.tune(variant=args.variant)
+    if args.pipeline is not None:
+        G.tune(pipeline=args.pipeline)
     eps, delta = extra["eps"], extra["delta"]
     for w in range(args.warmup):
         t = time.perf_counter()

@@ -204,12 +204,16 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
 oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
 /* Queued RSA rounds.  In steps 2 and 3 of the RSA estimator (Alg. 3) the
  * number of samples is fixed when the step starts, so a round that neither
- * starts nor ends a step determines the next one: with enable != 0 (the
- * default) the next round is queued on the stream before this one's sums are
- * read back, and the GPU does not wait for the host between them; 0 reads
- * every round back before planning the next.  Results do not depend on it.
- * Errors: OI_EINVAL for a null graph. */
-oi_status oi_set_pipeline(oi_graph* g, int enable);
+ * starts nor ends a step determines the next one.  mode 1 (the default):
+ * the next round is queued on the stream before this one's sums are read
+ * back, and the GPU does not wait for the host between them; 2: as 1, and
+ * every round (table uploads, sampling kernels, reductions, read-back) is
+ * captured as one graph and launched with one call (while event timing is
+ * on, rounds are issued as in mode 1); 0: every round is read back before
+ * the next is planned.  Results
+ * do not depend on the mode.  Errors: OI_EINVAL for a null graph or a mode
+ * outside 0..2. */
+oi_status oi_set_pipeline(oi_graph* g, int mode);
 /* What oi_autotune chose and measured. */
 typedef struct {
   int32_t variant;      /* small-kernel variant */

@@ -254,8 +254,9 @@ def oi_set_routing(g, small_direct=-1, large_qcap=-1):
     _check("oi_set_routing", _lib.oi_set_routing(g, int(small_direct), int(large_qcap)))
 
 
-def oi_set_pipeline(g, enable):
-    _check("oi_set_pipeline", _lib.oi_set_pipeline(g, 1 if enable else 0))
+def oi_set_pipeline(g, mode):
+    """0: read every RSA round back; 1: queue rounds whose plan is fixed; 2: as 1, one graph per round."""
+    _check("oi_set_pipeline", _lib.oi_set_pipeline(g, int(mode)))
 
 
 def oi_autotune(g, seed_off, seeds, query_ids, pilot, run_seed):

@@ -1390,7 +1390,21 @@ __global__ void __launch_bounds__(256) chunk_sums_kernel(const uint32_t* y, uint
   const uint64_t b = c * ch;
   const uint64_t e = b + ch < count ? b + ch : count;
   unsigned long long s = 0;
-  for (uint64_t i = b + threadIdx.x; i < e; i += 256) s += y[i];
+  // 16-byte loads, four in flight per thread (b is a multiple of ch, which
+  // is a multiple of 4), then the ragged tail one value at a time
+  const uint64_t nv = (e - b) >> 2;
+  const uint4* v = reinterpret_cast<const uint4*>(y + b);
+  for (uint64_t k0 = threadIdx.x; k0 < nv; k0 += 4 * 256) {
+    uint4 r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const uint64_t k = k0 + (uint64_t)u * 256;
+      r[u] = k < nv ? v[k] : make_uint4(0u, 0u, 0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) s += (unsigned long long)r[u].x + r[u].y + r[u].z + r[u].w;
+  }
+  for (uint64_t i = b + 4 * nv + threadIdx.x; i < e; i += 256) s += y[i];
 #pragma unroll
   for (int d = 32; d > 0; d >>= 1) s += __shfl_down(s, d, 64);
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
@@ -1398,8 +1412,13 @@ __global__ void __launch_bounds__(256) chunk_sums_kernel(const uint32_t* y, uint
   if (threadIdx.x == 0) out[c] = part[0] + part[1] + part[2] + part[3];
 }
 
+constexpr uint64_t kPairsPerBlock = 16384;  // pair kernel: 128 KB of Y per block
+
 // 128-bit sums of (y[2i] - y[2i+1])^2 per pair segment.  Each term is below
-// 2^62; partial sums are carried as (lo, hi) pairs.
+// 2^62; partial sums are carried as (lo, hi) pairs.  A segment's accumulator
+// is two words (w0, w1) with sum = w0 + w1 * 2^32: an update adds the low 32
+// bits of a partial sum to w0 and the rest to w1, so its two atomics need
+// no returned value (w0 stays below 2^32 times the number of updates).
 struct PairSeg {
   uint64_t out_off;  // first Y of the segment in y
   uint64_t npairs;
@@ -1420,28 +1439,45 @@ __device__ __forceinline__ void flush128(unsigned long long* acc, unsigned long 
   atomicAdd(&acc[1], hi + (old + lo < old ? 1ull : 0ull));
 }
 
+// Pair segment holding flat pair index x (flat0 strictly increases: every
+// pair segment has at least one pair).
+__device__ __forceinline__ int32_t pair_segment(const PairSeg* ps, int32_t nps, uint64_t x) {
+  int32_t a = 0, b = nps - 1;
+  while (a < b) {
+    const int32_t mid = (a + b + 1) >> 1;
+    if (ps[mid].flat0 <= x)
+      a = mid;
+    else
+      b = mid - 1;
+  }
+  return a;
+}
+
+__device__ __forceinline__ void add_limbs(unsigned long long* acc, unsigned long long L, unsigned long long H) {
+  // a partial sum below 2^96 (at most 2^31 pairs of terms below 2^62), so
+  // H * 2^32 fits in 64 bits
+  if (L | H) {
+    atomicAdd(&acc[0], L & 0xFFFFFFFFull);
+    atomicAdd(&acc[1], (L >> 32) | (H << 32));
+  }
+}
+
 // One pass per block over a contiguous range of pairs; partial sums are
-// reduced across the block before a single 128-bit atomic per segment run.
+// reduced across the block.  The block's first segment run goes to its
+// own slot of `part` (no atomics: a launch over one segment would otherwise
+// serialise on one address), later runs (past a segment boundary, rare) to
+// the segment's accumulator.
 __global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const PairSeg* ps, int32_t nps,
-                                                      uint64_t total, uint64_t per_block, unsigned long long* acc) {
+                                                      uint64_t total, uint64_t per_block, unsigned long long* acc,
+                                                      unsigned long long* part) {
   __shared__ unsigned long long red_lo[4], red_hi[4];
   const uint64_t b0 = (uint64_t)blockIdx.x * per_block;
   const uint64_t b1 = b0 + per_block < total ? b0 + per_block : total;
   if (b0 >= b1) return;
   // segment of the block's first pair; blocks are small next to segments,
   // so a block crosses few segment boundaries
-  int32_t seg = 0;
-  {
-    int32_t a = 0, b = nps - 1;
-    while (a < b) {
-      const int32_t mid = (a + b + 1) >> 1;
-      if (ps[mid].flat0 <= b0)
-        a = mid;
-      else
-        b = mid - 1;
-    }
-    seg = a;
-  }
+  int32_t seg = pair_segment(ps, nps, b0);
+  bool first = true;
   uint64_t lo_pair = b0;
   while (lo_pair < b1 && seg < nps) {
     const PairSeg P = ps[seg];
@@ -1466,16 +1502,16 @@ __global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const P
       ++a;
     }
     const uint64_t q0 = a >> 1, q1 = b >> 1;  // whole groups of two pairs
-    for (uint64_t q = q0 + threadIdx.x; q < q1; q += 2 * 256) {
-      uint4 v[2];
+    for (uint64_t q = q0 + threadIdx.x; q < q1; q += 8 * 256) {
+      uint4 v[8];  // eight 16-byte loads in flight per thread
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const uint64_t qq = q + (uint64_t)u * 256;
         v[u] = make_uint4(0u, 0u, 0u, 0u);
         if (qq < q1) v[u] = *reinterpret_cast<const uint4*>(&yb[4 * qq]);
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < 8; ++u) {
         const unsigned long long d0 =
             v[u].x > v[u].y ? (unsigned long long)(v[u].x - v[u].y) : (unsigned long long)(v[u].y - v[u].x);
         const unsigned long long d1 =
@@ -1502,12 +1538,39 @@ __global__ void __launch_bounds__(256) pair_sq_kernel(const uint32_t* y, const P
     if (threadIdx.x == 0) {
       unsigned long long L = 0, H = 0;
       for (int w = 0; w < 4; ++w) add128(L, H, red_lo[w], red_hi[w]);
-      if (L | H) flush128(&acc[2 * P.acc], L, H);
+      if (first) {
+        part[2 * blockIdx.x] = L;
+        part[2 * blockIdx.x + 1] = H;
+      } else {
+        add_limbs(&acc[2 * P.acc], L, H);
+      }
     }
+    first = false;
     __syncthreads();
     lo_pair = hi_pair;
     ++seg;
   }
+}
+
+// Adds each pair_sq block's first-run partial to its segment's accumulator:
+// one block; thread t takes blocks t, t + 256, ... (independent loads) and
+// makes one update per change of segment.
+__global__ void __launch_bounds__(256) pair_reduce_kernel(const PairSeg* ps, int32_t nps, uint64_t nblocks,
+                                                          uint64_t per_block, const unsigned long long* part,
+                                                          unsigned long long* acc) {
+  int32_t cur = -1;
+  unsigned long long L = 0, H = 0;
+#pragma unroll 4
+  for (uint64_t k = threadIdx.x; k < nblocks; k += 256) {
+    const int32_t j = nps == 1 ? 0 : pair_segment(ps, nps, k * per_block);
+    if (j != cur) {
+      if (cur >= 0) add_limbs(&acc[2 * ps[cur].acc], L, H);
+      cur = j;
+      L = H = 0;
+    }
+    add128(L, H, part[2 * k], part[2 * k + 1]);
+  }
+  if (cur >= 0) add_limbs(&acc[2 * ps[cur].acc], L, H);
 }
 
 // ---------------------------------------------------------------------------
@@ -1761,17 +1824,35 @@ hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, uns
                              hipStream_t st) {
   const uint64_t nc = (count + ch - 1) / ch;
   if (nc == 0) return hipSuccess;
+  if (ch % 4) return hipErrorInvalidValue;  // chunks start 16-byte aligned
   hipLaunchKernelGGL(chunk_sums_kernel, dim3((unsigned)nc), dim3(256), 0, st, y, count, ch, out);
   return hipGetLastError();
 }
 
+__global__ void __launch_bounds__(256) clear_u64_kernel(unsigned long long* p, uint64_t n) {
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = 0ull;
+}
+
+hipError_t launch_clear_u64(unsigned long long* p, uint64_t n, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  const uint64_t want = (n + 255) / 256, blocks = want < 1024 ? want : 1024;
+  hipLaunchKernelGGL(clear_u64_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n);
+  return hipGetLastError();
+}
+
+uint64_t pair_sq_blocks(uint64_t total) { return (total + kPairsPerBlock - 1) / kPairsPerBlock; }
+
+// part: 2 words per block (pair_sq_blocks(total) blocks)
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
-                          hipStream_t st) {
+                          unsigned long long* part, hipStream_t st) {
   if (total == 0) return hipSuccess;
-  const uint64_t per_block = 16384;  // pairs per block: 128 KB of Y
-  const uint64_t blocks = (total + per_block - 1) / per_block;
-  hipLaunchKernelGGL(pair_sq_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y,
-                     reinterpret_cast<const PairSeg*>(ps), nps, total, per_block, acc);
+  const uint64_t blocks = pair_sq_blocks(total);
+  const PairSeg* p = reinterpret_cast<const PairSeg*>(ps);
+  hipLaunchKernelGGL(pair_sq_kernel, dim3((unsigned)blocks), dim3(256), 0, st, y, p, nps, total, kPairsPerBlock,
+                     acc, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(pair_reduce_kernel, dim3(1), dim3(256), 0, st, p, nps, blocks, kPairsPerBlock, part, acc);
   return hipGetLastError();
 }
 

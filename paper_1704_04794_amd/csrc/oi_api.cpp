@@ -33,7 +33,9 @@ hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu);
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, unsigned long long* out, hipStream_t st);
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
-                          hipStream_t st);
+                          unsigned long long* part, hipStream_t st);
+uint64_t pair_sq_blocks(uint64_t total);
+hipError_t launch_clear_u64(unsigned long long* p, uint64_t n, hipStream_t st);
 size_t pair_seg_size();
 hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float* p_out, hipStream_t st);
 hipError_t launch_probe_nodes(const EdgeGroup* eg, int64_t m, uint64_t count, uint32_t seed, int32_t* nodes,
@@ -148,9 +150,10 @@ enum Phase { P_DONE = 0, P_STEP1 = 1, P_STEP2 = 2, P_STEP3 = 3 };
 // that is cleared before and copied to page-locked memory after the round.
 // Two slots let the next round be queued before this one is read back.
 struct RoundSlot {
-  DevBuf d_segs, d_qs, d_pairs, d_res;
+  DevBuf d_segs, d_qs, d_pairs, d_res, d_ppart;
   PinBuf h_segs, h_qs, h_pairs, h_res;
   hipEvent_t ev[7] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // [6]: round done
+  hipGraphExec_t exec = nullptr;  // the round as a graph (queued rounds in graph mode)
   std::vector<const HostQuery*> qv;
   std::vector<SegReq> segs;
   std::vector<int> seg_owner;
@@ -164,6 +167,7 @@ struct RoundSlot {
   ~RoundSlot() {
     for (hipEvent_t& e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (exec) (void)hipGraphExecDestroy(exec);
   }
   size_t sums_at() const { return 16; }
   size_t pacc_at() const { return 16 + 2 * segs.size(); }
@@ -196,7 +200,10 @@ struct oi_graph {
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
   uint64_t round_max = 1ull << 28;  // samples per launch: 1 GiB of Y, 2 GiB per hand-over list
   RoundSlot slots[2];
-  bool pipeline = true;             // queue a round whose plan is known before the last is read back
+  // 1: queue a round whose plan is known before the last is read back; 2:
+  // also launch each round as one captured graph; 0: neither
+  int pipeline = 1;
+  hipStream_t cap_stream = nullptr;  // graph capture (never runs work itself)
   // timing
   bool timing = false;
   hipEvent_t ev[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
@@ -426,12 +433,12 @@ oi::SampleLaunch make_giant_launch(const oi_graph* g, const oi::SampleLaunch& A,
   return B;
 }
 
-// tiny -> small -> large kernels of one launch over A.total samples; ev
-// (four events, or null) brackets the three.
-oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t* ev) {
+// tiny -> small -> large kernels of one launch over A.total samples on
+// stream st; ev (four events, or null) brackets the three.
+oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t* ev, hipStream_t st) {
   const uint64_t want_waves = (A.total + 63) / 64;
   int bpc = 0;
-  if (ev) HIP_TRY(hipEventRecord(ev[0], g->stream));
+  if (ev) HIP_TRY(hipEventRecord(ev[0], st));
   if (g->use_tiny) {
     HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
     if (bpc < 1) bpc = 1;
@@ -440,9 +447,9 @@ oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t
       const uint64_t c = A.total / ((uint64_t)blocks * 4 * 8);
       A.tiny_chunk = (uint32_t)std::min<uint64_t>(2048, std::max<uint64_t>(256, c));
     }
-    HIP_TRY(oi::launch_tiny(is_bwd, A, blocks, g->stream));
+    HIP_TRY(oi::launch_tiny(is_bwd, A, blocks, st));
   }
-  if (ev) HIP_TRY(hipEventRecord(ev[1], g->stream));
+  if (ev) HIP_TRY(hipEventRecord(ev[1], st));
   HIP_TRY(oi::small_occupancy(g->variant, is_bwd, &bpc));
   if (bpc < 1) bpc = 1;
   {
@@ -450,11 +457,11 @@ oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t
     // must not depend on that count (it is on the device), so it is sized
     // for the whole launch and idle waves exit at once
     const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
-    HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, g->stream));
+    HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, st));
   }
-  if (ev) HIP_TRY(hipEventRecord(ev[2], g->stream));
-  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, g->stream));
-  if (ev) HIP_TRY(hipEventRecord(ev[3], g->stream));
+  if (ev) HIP_TRY(hipEventRecord(ev[2], st));
+  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, st));
+  if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return OI_OK;
 }
 
@@ -524,7 +531,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     A.acc_dead = bwd->dead;
     A.acc_tab = bwd->tab;
   }
-  OI_TRY(launch_tiers(g, A, is_bwd, g->timing ? g->ev : nullptr));
+  OI_TRY(launch_tiers(g, A, is_bwd, g->timing ? g->ev : nullptr, g->stream));
   unsigned long long hctl[16] = {0};
   HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
@@ -753,34 +760,75 @@ oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
   HIP_TRY(S.d_qs.ensure(S.qv.size() * sizeof(oi::QueryDev)));
   HIP_TRY(S.d_pairs.ensure(S.pair_seg.size() * sizeof(PairDesc)));
   HIP_TRY(S.d_res.ensure(words * 8));
+  HIP_TRY(S.d_ppart.ensure(oi::pair_sq_blocks(S.ptotal) * 2 * sizeof(unsigned long long)));
   // the hand-over lists are shared by the queued rounds: growing them waits
   // for the round in flight
   if (g->d_def.bytes < total * sizeof(unsigned long long) || g->d_def2.bytes < total * sizeof(unsigned long long))
     HIP_TRY(hipStreamSynchronize(g->stream));
   HIP_TRY(g->d_def.ensure(total * sizeof(unsigned long long)));
   HIP_TRY(g->d_def2.ensure(total * sizeof(unsigned long long)));
-  HIP_TRY(hipMemcpyAsync(S.d_segs.p, ds, ns * sizeof(oi::Segment), hipMemcpyHostToDevice, g->stream));
-  HIP_TRY(hipMemcpyAsync(S.d_qs.p, qd, S.qv.size() * sizeof(oi::QueryDev), hipMemcpyHostToDevice, g->stream));
-  if (!S.pair_seg.empty())
-    HIP_TRY(hipMemcpyAsync(S.d_pairs.p, pd, S.pair_seg.size() * sizeof(PairDesc), hipMemcpyHostToDevice, g->stream));
   unsigned long long* res = S.d_res.as<unsigned long long>();
-  HIP_TRY(hipMemsetAsync(res, 0, S.chunks_at() * 8, g->stream));
   uint32_t* ydev = g->d_y.as<uint32_t>();
   oi::SampleLaunch A = make_launch(g, S.d_segs.as<oi::Segment>(), S.d_qs.as<oi::QueryDev>(), (int32_t)ns, total,
                                    seed, S.write_y ? ydev : nullptr, nullptr, res, res + S.sums_at());
   S.timed = g->timing;
-  OI_TRY(launch_tiers(g, A, false, S.timed ? S.ev : nullptr));
-  if (S.giant_inline) {
-    const oi::SampleLaunch B = make_giant_launch(g, A, res);
-    if (S.timed) HIP_TRY(hipEventRecord(S.ev[4], g->stream));
-    HIP_TRY(oi::launch_large_full(false, B, g->giant_blocks, g->stream));
-    if (S.timed) HIP_TRY(hipEventRecord(S.ev[5], g->stream));
+  // every operation of the round, in stream order (the result block is
+  // cleared by a kernel: no memset node may enter a captured graph)
+  auto issue = [&](hipStream_t st) -> oi_status {
+    HIP_TRY(hipMemcpyAsync(S.d_segs.p, ds, ns * sizeof(oi::Segment), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(S.d_qs.p, qd, S.qv.size() * sizeof(oi::QueryDev), hipMemcpyHostToDevice, st));
+    if (!S.pair_seg.empty())
+      HIP_TRY(hipMemcpyAsync(S.d_pairs.p, pd, S.pair_seg.size() * sizeof(PairDesc), hipMemcpyHostToDevice, st));
+    HIP_TRY(oi::launch_clear_u64(res, S.chunks_at(), st));
+    OI_TRY(launch_tiers(g, A, false, S.timed ? S.ev : nullptr, st));
+    if (S.giant_inline) {
+      const oi::SampleLaunch B = make_giant_launch(g, A, res);
+      if (S.timed) HIP_TRY(hipEventRecord(S.ev[4], st));
+      HIP_TRY(oi::launch_large_full(false, B, g->giant_blocks, st));
+      if (S.timed) HIP_TRY(hipEventRecord(S.ev[5], st));
+    }
+    if (S.nch) HIP_TRY(oi::launch_chunk_sums(ydev, S.off, kChunk, res + S.chunks_at(), st));
+    if (S.ptotal)
+      HIP_TRY(oi::launch_pair_sq(ydev, S.d_pairs.p, (int32_t)S.pair_seg.size(), S.ptotal, res + S.pacc_at(),
+                                 S.d_ppart.as<unsigned long long>(), st));
+    HIP_TRY(hipMemcpyAsync(S.h_res.p, res, words * 8, hipMemcpyDeviceToHost, st));
+    return OI_OK;
+  };
+  if (g->pipeline == 2 && !S.timed) {
+    // the round as one graph: captured on a stream of the library's own,
+    // launched on the caller's stream (the executable graph of the slot is
+    // updated in place when the round has the same shape as the last one).
+    // Events recorded inside a graph cannot be timed, so with event timing
+    // on the round is issued operation by operation.
+    if (!g->cap_stream) HIP_TRY(hipStreamCreateWithFlags(&g->cap_stream, hipStreamNonBlocking));
+    HIP_TRY(hipStreamBeginCapture(g->cap_stream, hipStreamCaptureModeThreadLocal));
+    const oi_status st = issue(g->cap_stream);
+    hipGraph_t gr = nullptr;
+    const hipError_t ec = hipStreamEndCapture(g->cap_stream, &gr);
+    if (st != OI_OK || ec != hipSuccess) {
+      if (gr) (void)hipGraphDestroy(gr);
+      if (st != OI_OK) return st;
+      HIP_TRY(ec);
+    }
+    bool updated = false;
+    if (S.exec) {
+      hipGraphNode_t bad = nullptr;
+      hipGraphExecUpdateResult ur = hipGraphExecUpdateSuccess;
+      updated = hipGraphExecUpdate(S.exec, gr, &bad, &ur) == hipSuccess && ur == hipGraphExecUpdateSuccess;
+      (void)hipGetLastError();
+      if (!updated) {
+        (void)hipGraphExecDestroy(S.exec);
+        S.exec = nullptr;
+      }
+    }
+    hipError_t e = hipSuccess;
+    if (!updated) e = hipGraphInstantiate(&S.exec, gr, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(gr);
+    HIP_TRY(e);
+    HIP_TRY(hipGraphLaunch(S.exec, g->stream));
+  } else {
+    OI_TRY(issue(g->stream));
   }
-  if (S.nch) HIP_TRY(oi::launch_chunk_sums(ydev, S.off, kChunk, res + S.chunks_at(), g->stream));
-  if (S.ptotal)
-    HIP_TRY(oi::launch_pair_sq(ydev, S.d_pairs.p, (int32_t)S.pair_seg.size(), S.ptotal, res + S.pacc_at(),
-                               g->stream));
-  HIP_TRY(hipMemcpyAsync(S.h_res.p, res, words * 8, hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipEventRecord(S.ev[6], g->stream));
   return OI_OK;
 }
@@ -829,7 +877,7 @@ oi_status absorb_round(oi_graph* g, std::vector<Rsa>& rs, RoundSlot& S, uint32_t
     R.r.sum_y += sums[2 * i];
     R.r.edges_examined += sums[2 * i + 1];
     if (S.seg_phase[i] == P_STEP2) {
-      R.D += ((u128)pacc[2 * pj + 1] << 64) | (u128)pacc[2 * pj];
+      R.D += (u128)pacc[2 * pj] + ((u128)pacc[2 * pj + 1] << 32);  // w0 + w1 * 2^32
       ++pj;
       if (sq.first / 2 + sq.count / 2 == R.r.nsigma) OI_TRY(set_step3(g, R, seed, &R.r.rounds));
     } else if (S.seg_phase[i] == P_STEP1) {
@@ -954,7 +1002,7 @@ oi_status rsa_drive_rounds(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
     ++inflight;
     // advance the counts the plan fixes; a round that starts or ends a
     // phase is read back before anything else is planned
-    const bool can_queue = g->pipeline && (S.giant_inline || (int64_t)g->large_qcap >= g->n);
+    const bool can_queue = g->pipeline > 0 && (S.giant_inline || (int64_t)g->large_qcap >= g->n);
     bool ends = !can_queue;
     for (size_t i = 0; i < S.segs.size(); ++i) {
       Rsa& R = rs[S.seg_owner[i]];
@@ -1208,6 +1256,7 @@ oi_status oi_set_stream(oi_graph* g, void* hip_stream) {
 void oi_graph_destroy(oi_graph* g) {
   if (!g) return;
   (void)hipStreamSynchronize(g->stream);
+  if (g->cap_stream) (void)hipStreamDestroy(g->cap_stream);
   for (int i = 0; i < 6; ++i)
     if (g->ev[i]) (void)hipEventDestroy(g->ev[i]);
   delete g;
@@ -1492,9 +1541,10 @@ oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap) {
   return OI_OK;
 }
 
-oi_status oi_set_pipeline(oi_graph* g, int enable) {
+oi_status oi_set_pipeline(oi_graph* g, int mode) {
   if (!g) return fail(OI_EINVAL, "null graph");
-  g->pipeline = enable != 0;
+  if (mode < 0 || mode > 2) return fail(OI_EINVAL, "pipeline mode must be 0, 1 or 2");
+  g->pipeline = mode;
   return OI_OK;
 }
 

@@ -66,10 +66,10 @@ def test_rsa_small_rounds_same_answer(P):
 
 
 def test_queued_rounds_same_answer(P):
-    """Rounds queued before the previous one is read back (steps 2 and 3)
-    give exactly the results of rounds read back one at a time, also when a
-    sample outgrows the large kernel's queues and its round is run again
-    with the full-size pass."""
+    """Rounds queued before the previous one is read back (steps 2 and 3),
+    also as one captured graph per round, give exactly the results of rounds
+    read back one at a time, also when a sample outgrows the large kernel's
+    queues and its round is run again with the full-size pass."""
     g = chung_lu_graph(20000, 200000, 2.1, 7)
     gw = g.with_p(wc_probs(g))
     rng = np.random.default_rng(11)
@@ -77,20 +77,31 @@ def test_queued_rounds_same_answer(P):
     keys = FIELDS + ("oi", "is_", "mu", "mu1", "samples_x", "samples_xp", "rounds", "sum_y", "edges_examined")
     for qcap in (-1, 24):
         res = {}
-        for pipe in (False, True):
-            print(f"[gpu] queued rounds pipeline={pipe} large_qcap={qcap}", flush=True)
+        # the third run starts every sample in the small kernel; the fourth
+        # launches every round as one captured graph
+        for key, pipe, tiny in ((0, 0, 1), (1, 1, 1), (2, 1, 0), (3, 2, 1)):
+            print(f"[gpu] queued rounds pipeline={pipe} tiny={tiny} large_qcap={qcap}", flush=True)
             G = P.Graph.from_inputs(gw)
-            G.tune(round_max=16384, large_qcap=qcap, pipeline=pipe)
-            res[pipe] = (G.estimate_batch(sets, 0.2, 1e-2, mode=0, query_ids=np.arange(5, dtype=np.uint32)),
-                         [G.estimate(sets[0], 0.1, 1e-2, mode=1, query_id=9)])
+            G.tune(round_max=16384, large_qcap=qcap, pipeline=pipe, tiny=tiny)
+            res[key] = (G.estimate_batch(sets, 0.2, 1e-2, mode=0, query_ids=np.arange(5, dtype=np.uint32)),
+                        [G.estimate(sets[0], 0.1, 1e-2, mode=1, query_id=9)])
+            if pipe == 2:  # with event timing on, rounds are issued one operation at a time
+                G.timing(True)
+                again = G.estimate(sets[0], 0.1, 1e-2, mode=1, query_id=9)
+                tm = G.timing()
+                G.timing(False)
+                assert again["oi"] == res[key][1][0]["oi"] and again["T"] == res[key][1][0]["T"]
+                assert tm["launches"] > 4 and tm["tiny_ms"] > 0 and tm["samples"] > 0
             G.close()
-        for a_list, b_list in zip(res[False], res[True]):
-            for a, b in zip(a_list, b_list):
-                for f in keys:
-                    assert a[f] == b[f], (qcap, f, a[f], b[f])
-        assert res[True][1][0]["rounds"] > 4
+        for other in (1, 2, 3):
+            for a_list, b_list in zip(res[0], res[other]):
+                for a, b in zip(a_list, b_list):
+                    for f in keys:
+                        assert a[f] == b[f], (qcap, other, f, a[f], b[f])
+        assert res[1][1][0]["rounds"] > 4
+    one = res[1][1][0]
     b = O.estimate(gw, sets[0], 0.1, 1e-2, 1, 9, RUN_SEED)
-    assert res[True][1][0]["oi"] == b["oi"] and res[True][1][0]["T"] == b["rsa"]["T"]
+    assert one["oi"] == b["oi"] and one["T"] == b["rsa"]["T"] and one["D"] == b["rsa"]["D"]
 
 
 def test_rsa_chung_lu(P):
