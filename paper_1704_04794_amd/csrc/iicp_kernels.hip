@@ -33,6 +33,12 @@ struct Words {
   uint32_t w[4];
 };
 
+// a ^ b ^ c in one instruction (gfx950's three-input bitwise operation;
+// 0x96 is the truth table of the three-way exclusive or)
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 __device__ __forceinline__ Words philox_draw(uint32_t k0, uint32_t k1, uint32_t kind, uint32_t stream,
                                              uint64_t s, uint64_t idx) {
   uint32_t c0 = (uint32_t)idx, c1 = (uint32_t)(idx >> 32), c2 = (uint32_t)s;
@@ -45,8 +51,8 @@ __device__ __forceinline__ Words philox_draw(uint32_t k0, uint32_t k1, uint32_t 
     }
     const uint64_t a = (uint64_t)0xD2511F53u * (uint64_t)c0;
     const uint64_t b = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
-    const uint32_t n0 = (uint32_t)(b >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(a >> 32) ^ c3 ^ k1;
+    const uint32_t n0 = xor3((uint32_t)(b >> 32), c1, k0);
+    const uint32_t n2 = xor3((uint32_t)(a >> 32), c3, k1);
     c1 = (uint32_t)b;
     c3 = (uint32_t)a;
     c0 = n0;
@@ -103,10 +109,10 @@ __device__ __forceinline__ int32_t tab_v(const TabGroup* base, int64_t j) {
   return *(const OI_GLOBAL int32_t*)(p + 4 * (j & 3));
 }
 
-// Live iff word < floor(p * 2^32).  p * 2^32 is exact in fp32 for p in [0, 1)
-// and the conversion truncates, which is the floor; p = 1 is always live.
-__device__ __forceinline__ bool edge_live(uint32_t word, float p) {
-  return p >= 1.0f || word < (uint32_t)(p * 4294967296.0f);
+// Live iff word < floor(p * 2^32); p = 1 (threshold kThrAlways) is always
+// live.  See coin_threshold.
+__device__ __forceinline__ bool edge_live(uint32_t word, uint32_t thr) {
+  return word < thr || thr == kThrAlways;
 }
 
 // Alg. 1, Stage 1 selection: t = U * beta_0, i = min{j : CDF_j > t}; if no
@@ -454,13 +460,19 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     const v4i32 rc = *(const OI_GLOBAL v4i32*)lc;
     Words d;
     d.w[0] = d.w[1] = d.w[2] = d.w[3] = 0;
+    // the run seed (key word 1) stays a scalar: the empty asm makes it look
+    // new each iteration, so its ten round keys are formed with scalar adds
+    // here instead of being kept across the loop (where they would spill
+    // to vector lanes and each cost a vector read per round)
+    uint32_t seed = A.seed;
+    asm volatile("" : "+s"(seed));
     if (st == T_START || st == T_STAGE1 || st == T_EXPAND) {
       const uint32_t kind = st == T_START ? KIND_SELECT : (st == T_STAGE1 ? KIND_STAGE1 : KIND_EDGE);
-      d = philox_draw(qid, A.seed, kind, stream, s, st == T_START ? 0ull : (uint64_t)g);
+      d = philox_draw(qid, seed, kind, stream, s, st == T_START ? 0ull : (uint64_t)g);
     }
     // (4) consume
     const int32_t tv[4] = {ra.x, ra.y, ra.z, ra.w};
-    const float tp[4] = {__int_as_float(rb.x), __int_as_float(rb.y), __int_as_float(rb.z), __int_as_float(rb.w)};
+    const uint32_t tp[4] = {(uint32_t)rb.x, (uint32_t)rb.y, (uint32_t)rb.z, (uint32_t)rb.w};
     const uint64_t tt[4] = {(uint64_t)(uint32_t)rb.x | ((uint64_t)(uint32_t)rb.y << 32),
                             (uint64_t)(uint32_t)rb.z | ((uint64_t)(uint32_t)rb.w << 32),
                             (uint64_t)(uint32_t)rc.x | ((uint64_t)(uint32_t)rc.y << 32),
@@ -955,9 +967,9 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         if (kd == ITEM_NODE) {
           const Words d = philox_draw(qid, A.seed, KIND_EDGE, stream, s, g);
           const int4 vv = *reinterpret_cast<const int4*>(&A.eg[g].v[0]);
-          const float4 pp = *reinterpret_cast<const float4*>(&A.eg[g].p[0]);
+          const uint4 pp = *reinterpret_cast<const uint4*>(&A.eg[g].thr[0]);
           const int32_t va[4] = {vv.x, vv.y, vv.z, vv.w};
-          const float pa[4] = {pp.x, pp.y, pp.z, pp.w};
+          const uint32_t pa[4] = {pp.x, pp.y, pp.z, pp.w};
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const int64_t e = 4 * (int64_t)g + b;
@@ -1326,7 +1338,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
           for (int b = 0; b < 4; ++b) {
             const uint32_t e = 4 * gg[u] + b;
             if (e >= lo_e[u] && e < hi_e[u]) {
-              const bool live = edge_live(d[u].w[b], __int_as_float(pa[u][b]));
+              const bool live = edge_live(d[u].w[b], (uint32_t)pa[u][b]);
               const int32_t v = va[u][b];
               if (BWD) {
                 // an edge into S is never revealed (its target is not outside S)
@@ -1577,13 +1589,13 @@ __global__ void __launch_bounds__(256) pair_reduce_kernel(const PairSeg* ps, int
 // backward finishing: integer Y-sums -> fp32 gradient
 // ---------------------------------------------------------------------------
 // Stage-2 edges: g_p = scale * (L/p - D/(1-p)), g_theta = scale * (L(1-p) - D p).
-__global__ void __launch_bounds__(256) bwd_edges_kernel(const EdgeGroup* eg, int64_t m,
+__global__ void __launch_bounds__(256) bwd_edges_kernel(const float* pe_arr, int64_t m,
                                                         const unsigned long long* acc_live,
                                                         const unsigned long long* acc_dead, double scale,
                                                         int theta, float* grad) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
-    const double p = (double)eg[e >> 2].p[e & 3];
+    const double p = (double)pe_arr[e];
     const unsigned long long L = acc_live[e], D = acc_dead[e];
     double g = 0.0;
     if (theta) {
@@ -1600,7 +1612,7 @@ __global__ void __launch_bounds__(256) bwd_edges_kernel(const EdgeGroup* eg, int
 
 // S-edges into Stage-1 entry j: x_j = 1 contributes A_j * prod_{f != e}(1 - p_f) / P_j,
 // x_j = 0 contributes -B_j / (1 - p_e), B_j = sumY - A_j.
-__global__ void __launch_bounds__(256) bwd_stage1_kernel(const EdgeGroup* eg, const int64_t* se_off,
+__global__ void __launch_bounds__(256) bwd_stage1_kernel(const float* pe_arr, const int64_t* se_off,
                                                          const int64_t* se, const double* P, int64_t l,
                                                          const unsigned long long* acc_tab,
                                                          unsigned long long sumY, double scale, int theta,
@@ -1611,14 +1623,14 @@ __global__ void __launch_bounds__(256) bwd_stage1_kernel(const EdgeGroup* eg, co
     const int64_t b0 = se_off[j], b1 = se_off[j + 1];
     for (int64_t a = b0; a < b1; ++a) {
       const int64_t e = se[a];
-      const double pe = (double)eg[e >> 2].p[e & 3];
+      const double pe = (double)pe_arr[e];
       double live = 0.0, dead = 0.0;
       if (Aj) {
         double prod = 1.0;
         for (int64_t c = b0; c < b1; ++c)
           if (c != a) {
             const int64_t f = se[c];
-            prod = prod * (1.0 - (double)eg[f >> 2].p[f & 3]);
+            prod = prod * (1.0 - (double)pe_arr[f]);
           }
         live = (double)Aj * prod / P[j];
       }
@@ -1635,14 +1647,14 @@ __global__ void __launch_bounds__(256) bwd_stage1_kernel(const EdgeGroup* eg, co
   }
 }
 
-// p_e = sigmoid(theta_e) in fp64, rounded to fp32, written into the edge
-// groups and into a plain fp32 array.
+// p_e = sigmoid(theta_e) in fp64, rounded to fp32, written into the plain
+// fp32 array and, as coin thresholds, into the edge groups.
 __global__ void __launch_bounds__(256) theta_to_p_kernel(const float* theta, int64_t m, EdgeGroup* eg, float* p_out) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
     const double t = (double)theta[e];
     const float p = (float)(1.0 / (1.0 + exp(-t)));
-    eg[e >> 2].p[e & 3] = p;
+    eg[e >> 2].thr[e & 3] = coin_threshold(p);
     p_out[e] = p;
   }
 }
@@ -1866,22 +1878,22 @@ hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L,
+hipError_t launch_bwd_edges(const float* pe, int64_t m, const unsigned long long* L,
                             const unsigned long long* D, double scale, int theta, float* grad, hipStream_t st) {
   if (m == 0) return hipSuccess;
   int64_t blocks = (m + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, eg, m, L, D, scale, theta, grad);
+  hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, pe, m, L, D, scale, theta, grad);
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const int64_t* se, const double* P,
+hipError_t launch_bwd_stage1(const float* pe, const int64_t* se_off, const int64_t* se, const double* P,
                              int64_t l, const unsigned long long* acc_tab, unsigned long long sumY, double scale,
                              int theta, float* grad, hipStream_t st) {
   if (l == 0) return hipSuccess;
   int64_t blocks = (l + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(bwd_stage1_kernel, dim3((unsigned)blocks), dim3(256), 0, st, eg, se_off, se, P, l, acc_tab,
+  hipLaunchKernelGGL(bwd_stage1_kernel, dim3((unsigned)blocks), dim3(256), 0, st, pe, se_off, se, P, l, acc_tab,
                      sumY, scale, theta, grad);
   return hipGetLastError();
 }

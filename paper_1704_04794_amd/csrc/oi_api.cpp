@@ -42,9 +42,9 @@ hipError_t launch_probe_nodes(const EdgeGroup* eg, int64_t m, uint64_t count, ui
                               hipStream_t st);
 hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, const int32_t* nodes, uint64_t count,
                                unsigned long long* out, int cus, hipStream_t st);
-hipError_t launch_bwd_edges(const EdgeGroup* eg, int64_t m, const unsigned long long* L, const unsigned long long* D,
+hipError_t launch_bwd_edges(const float* pe, int64_t m, const unsigned long long* L, const unsigned long long* D,
                             double scale, int theta, float* grad, hipStream_t st);
-hipError_t launch_bwd_stage1(const EdgeGroup* eg, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
+hipError_t launch_bwd_stage1(const float* pe, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
                              const unsigned long long* acc_tab, unsigned long long sumY, double scale, int theta,
                              float* grad, hipStream_t st);
 }  // namespace oi
@@ -185,7 +185,7 @@ struct oi_graph {
   std::vector<int64_t> row_ptr;
   std::vector<int32_t> col;
   std::vector<float> p;
-  DevBuf d_row_ptr, d_eg;
+  DevBuf d_row_ptr, d_eg, d_p;  // d_p: fp32 p per edge (the backward's), beside the groups' thresholds
   // per-launch workspaces
   DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_bits, d_queue;
   int large_blocks = 0;
@@ -1101,10 +1101,12 @@ oi_status upload_graph(oi_graph* g) {
   std::memset(eg.data(), 0, eg.size() * sizeof(oi::EdgeGroup));
   for (int64_t e = 0; e < g->m; ++e) {
     eg[e >> 2].v[e & 3] = g->col[e];
-    eg[e >> 2].p[e & 3] = g->p[e];
+    eg[e >> 2].thr[e & 3] = oi::coin_threshold(g->p[e]);
   }
   HIP_TRY(g->d_eg.ensure(eg.size() * sizeof(oi::EdgeGroup)));
   HIP_TRY(hipMemcpy(g->d_eg.p, eg.data(), eg.size() * sizeof(oi::EdgeGroup), hipMemcpyHostToDevice));
+  HIP_TRY(g->d_p.ensure((size_t)std::max<int64_t>(g->m, 1) * sizeof(float)));
+  if (g->m) HIP_TRY(hipMemcpy(g->d_p.p, g->p.data(), (size_t)g->m * sizeof(float), hipMemcpyHostToDevice));
   return OI_OK;
 }
 
@@ -1224,18 +1226,18 @@ oi_status oi_graph_set_probs(oi_graph* g, const float* p, int device_ptr) {
 oi_status oi_graph_set_theta(oi_graph* g, const float* theta, int device_ptr) {
   if (!g || (g->m > 0 && !theta)) return fail(OI_EINVAL, "null argument");
   if (g->m == 0) return OI_OK;
-  DevBuf dt, dp;
+  DevBuf dt;
   const float* th = theta;
   if (!device_ptr) {
     HIP_TRY(dt.ensure((size_t)g->m * 4));
     HIP_TRY(hipMemcpy(dt.p, theta, (size_t)g->m * 4, hipMemcpyHostToDevice));
     th = dt.as<float>();
   }
-  HIP_TRY(dp.ensure((size_t)g->m * 4));
-  HIP_TRY(oi::launch_theta_to_p(th, g->m, g->d_eg.as<oi::EdgeGroup>(), dp.as<float>(), g->stream));
+  // p goes to the device p array and, as thresholds, to the edge groups
+  HIP_TRY(oi::launch_theta_to_p(th, g->m, g->d_eg.as<oi::EdgeGroup>(), g->d_p.as<float>(), g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
   // the host copy feeds the Stage-1 tables
-  HIP_TRY(hipMemcpy(g->p.data(), dp.p, (size_t)g->m * 4, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(g->p.data(), g->d_p.p, (size_t)g->m * 4, hipMemcpyDeviceToHost));
   for (float x : g->p)
     if (!(x >= 0.0f && x <= 1.0f)) return fail(OI_EINVAL, "theta gave a probability outside [0, 1]");
   return OI_OK;
@@ -1398,7 +1400,7 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
   const unsigned long long sumY = s[0];
   const double scale = grad_scale * Q.beta0 / (double)count;
   const int theta = param == OI_PARAM_THETA ? 1 : 0;
-  HIP_TRY(oi::launch_bwd_edges(g->d_eg.as<oi::EdgeGroup>(), g->m, bb.live, bb.dead, scale, theta, grad_out,
+  HIP_TRY(oi::launch_bwd_edges(g->d_p.as<float>(), g->m, bb.live, bb.dead, scale, theta, grad_out,
                                g->stream));
   HIP_TRY(seoff.ensure(Q.se_off.size() * 8));
   HIP_TRY(se.ensure(std::max<size_t>(Q.se.size(), 1) * 8));
@@ -1406,7 +1408,7 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
   HIP_TRY(hipMemcpy(seoff.p, Q.se_off.data(), Q.se_off.size() * 8, hipMemcpyHostToDevice));
   if (!Q.se.empty()) HIP_TRY(hipMemcpy(se.p, Q.se.data(), Q.se.size() * 8, hipMemcpyHostToDevice));
   if (!Q.P.empty()) HIP_TRY(hipMemcpy(P.p, Q.P.data(), Q.P.size() * 8, hipMemcpyHostToDevice));
-  HIP_TRY(oi::launch_bwd_stage1(g->d_eg.as<oi::EdgeGroup>(), seoff.as<int64_t>(), se.as<int64_t>(), P.as<double>(),
+  HIP_TRY(oi::launch_bwd_stage1(g->d_p.as<float>(), seoff.as<int64_t>(), se.as<int64_t>(), P.as<double>(),
                                 Q.l, bb.tab, sumY, scale, theta, grad_out, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
   return OI_OK;

@@ -9,13 +9,26 @@ namespace oi {
 
 // Out-edges in groups of four consecutive CSR edge ids (edge e lives in group
 // e/4, lane e%4).  One group is 32 bytes, so a sampler lane reads the targets
-// and probabilities of four edges with two 16-byte loads from one 64-byte
-// line, and the four coins of a group come from one Philox block.  Padding
-// entries past m have v = 0, p = 0 and are never inside a row range.
+// and coin thresholds of four edges with two 16-byte loads from one 64-byte
+// line, and the four coins of a group come from one Philox block.  The
+// threshold of an edge with probability p (fp32) is floor(p * 2^32) for
+// p < 1 (at most 2^32 - 256) and 0xFFFFFFFF for p = 1, which is thereby
+// unambiguous: the edge is live iff its coin word is below the threshold or
+// the threshold is 0xFFFFFFFF.  Padding entries past m have v = 0, thr = 0
+// and are never inside a row range.  The fp32 p themselves sit in a plain
+// array of their own (read by the backward only).
 struct alignas(32) EdgeGroup {
   int32_t v[4];
-  float p[4];
+  uint32_t thr[4];
 };
+
+constexpr uint32_t kThrAlways = 0xFFFFFFFFu;
+
+// The threshold of probability p in [0, 1] (fp32 arithmetic, exact: p * 2^32
+// only shifts the exponent, and the conversion truncates).
+__host__ __device__ inline uint32_t coin_threshold(float p) {
+  return p >= 1.0f ? kThrAlways : (uint32_t)(p * 4294967296.0f);
+}
 
 // Stage-1 table entries in groups of four (entry j in group j/4): the
 // neighbour v_j and its coin threshold floor(P_{S,v_j} * 2^32), which may be
