@@ -298,13 +298,20 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   const int32_t* c_shash = nullptr;
   // when the segment's Stage-1 table has a single entry, that entry v_0 and
   // its row bounds: every sample of the segment starts by popping v_0
-  int32_t c_v0 = 0;
+  int32_t c_v0 = 0, c_v0v = 0;
   int64_t c_rb0 = 0, c_re0 = 0;
+  // which per-sample outputs the launch wants, in one scalar word
+  const uint32_t outs = __builtin_amdgcn_readfirstlane((A.y_out ? 1u : 0u) | (A.e_out ? 2u : 0u));
   bool exhausted = false;
   uint32_t acc_seg = 0xFFFFFFFFu;
   unsigned long long acc_y = 0, acc_e = 0;
 
   while (true) {
+    // the output flags, tested where the outputs are written; the empty asm
+    // makes them look new each iteration, so the tests are not turned into
+    // lane masks kept (and spilled) across the loop
+    uint32_t o = outs;
+    asm volatile("" : "+s"(o));
     // (0) lanes whose queue is drained finish their sample.  A lane whose
     // sample belongs to another segment than its running sums flushes them
     // first; lanes reach segment ends at different times, so these atomics
@@ -314,8 +321,8 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       if (BWD) {
         if (cnt != y) atomicOr(A.err, 2u);
       } else {
-        if (A.y_out) A.y_out[oidx] = cnt;
-        if (A.e_out) A.e_out[oidx] = E;
+        if (o & 1u) A.y_out[oidx] = cnt;
+        if (o & 2u) A.e_out[oidx] = E;
       }
       if (sg != acc_seg) {
         if (acc_seg != 0xFFFFFFFFu) {
@@ -369,6 +376,11 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
             c_v0 = cptr(c_tab)->v[0];
             c_rb0 = cptr(A.row_ptr)[c_v0];
             c_re0 = cptr(A.row_ptr)[c_v0 + 1];
+            // v_0 is only ever stored to LDS: kept in a vector register
+            // (the empty asm places it there) it costs no scalar register
+            // across the loop and no move at each start
+            c_v0v = c_v0;
+            asm volatile("" : "+v"(c_v0v));
           }
         }
         const uint64_t lim = cend < cseg_end ? cend : cseg_end;
@@ -416,7 +428,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         // whatever U is, and no entry follows): v_0 is activated and, with
         // its row bounds read once per segment, popped at once, so the
         // sample examines its first edge group in this very iteration.
-        vis[0] = c_v0;
+        vis[0] = c_v0v;
         cnt = 1;
         qh = 1;
         E = (unsigned long long)(c_re0 - c_rb0);
