@@ -142,6 +142,9 @@ def test_batched_equals_single(P):
 def test_rsa_rejects_bad_parameters(P):
     g = tiny16_graph()
     G = P.Graph.from_inputs(g)
+    for mode in (-1, 3):
+        with pytest.raises(P.OiError):
+            G.tune(pipeline=mode)
     for eps, delta in [(0.0, 0.1), (1.0, 0.1), (0.1, 0.5), (0.1, 0.0), (float("nan"), 0.1)]:
         with pytest.raises(P.OiError):
             G.estimate([0], eps, delta)
