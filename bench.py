@@ -30,16 +30,16 @@ if ROOT not in sys.path:
 METRIC = "IICP samples/s + GTEPS; seed-set estimates/s batched vs single at ε=0.05"
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = 16  # row_ptr[u], row_ptr[u+1] (int64) per activated node
-BYTES_PER_EDGE = 8   # col (int32) + p (fp32) per examined edge
+BYTES_PER_EDGE = 8   # col (int32) + coin threshold (uint32) per examined edge
 
 
 # HBM bytes per tiny_kernel launch on the default workload, from two
 # rocprofv3 counter passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the scales a
-# 1 GiB device copy gives those counters), mean over the 20 launches of one
+# 1 GiB device copy gives those counters), mean over the 7 launches of one
 # estimate.  Reported only while the kernel sources (their code, comments
-# aside) hash to what was measured.
+# aside) hash to what was measured and an estimate takes as many launches.
 TRAFFIC = {"sources_sha1": "58cef95af3da3eb7cb9c2942abf3d3463ccee0e9", "kernel": "tiny_kernel",
-           "bytes_per_launch": 894468096.0, "l2_hit_rate": 0.785}
+           "launches_per_estimate": 7, "bytes_per_launch": 2563741388.8, "l2_hit_rate": 0.785}
 KERNEL_SOURCES = ("paper_1704_04794_amd/csrc/iicp_kernels.hip", "paper_1704_04794_amd/csrc/oi_device.hpp")
 
 
@@ -58,8 +58,9 @@ def kernel_sources_sha1():
     return h.hexdigest()
 
 
-def measured_traffic(kernel):
-    if kernel_sources_sha1() != TRAFFIC["sources_sha1"] or kernel != TRAFFIC["kernel"]:
+def measured_traffic(kernel, launches_per_estimate):
+    if (kernel_sources_sha1() != TRAFFIC["sources_sha1"] or kernel != TRAFFIC["kernel"]
+            or launches_per_estimate != TRAFFIC["launches_per_estimate"]):
         return None
     return TRAFFIC["bytes_per_launch"]
 
@@ -338,6 +339,7 @@ def main():
     kern = max(("tiny", "small", "large"), key=lambda k: tm[f"{k}_ms"])
     kbytes = BYTES_PER_NODE * tm[f"{kern}_y"] + BYTES_PER_EDGE * tm[f"{kern}_edges"]
     launches = max(tm["launches"], 1)
+    lpe = tm["launches"] / args.steps
     avg_ms = tm[f"{kern}_ms"] / launches
     achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
     out = {
@@ -361,8 +363,8 @@ def main():
         "samples_per_step": tot_samples / args.steps,
         "oi": res["oi"] if res else None,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{kern}_kernel"),
-                     "l2_hit_rate": TRAFFIC["l2_hit_rate"] if measured_traffic(f"{kern}_kernel") else None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{kern}_kernel", lpe),
+                     "l2_hit_rate": TRAFFIC["l2_hit_rate"] if measured_traffic(f"{kern}_kernel", lpe) else None,
                      "kernel": f"{kern}_kernel", "avg_launch_ms": avg_ms, "launches": tm["launches"],
                      "bytes_per_launch": kbytes / launches},
         "sampler": {k: tm[k] for k in ("tiny_ms", "small_ms", "large_ms", "samples", "handed_small",

@@ -190,7 +190,10 @@ oi_status oi_timing_get(oi_graph* g, oi_timing* out);
  * the one-sample-per-lane kernel first (default), 0 to start every sample in
  * the small kernel; tiny_chunk: samples the tiny kernel takes per increment
  * (0 = automatic, the default; negative keeps the current setting);
- * round_max: samples per sampling launch (multiple of 4096, default 2^28).  Negative (or
+ * round_max: samples per sampling launch (multiple of 4096, at most 2^31; the
+ * default, set at graph creation, is the largest power of two up to 2^30 whose
+ * round buffers, 36 bytes per sample, fit in a quarter of the free device
+ * memory).  Negative (or
  * zero) values keep the current setting.  Results do not depend on any of
  * these. */
 oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_chunk, int64_t round_max);

@@ -206,7 +206,10 @@ struct oi_graph {
   bool use_tiny = true;
   uint32_t chunk = 256;
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
-  uint64_t round_max = 1ull << 28;  // samples per launch: 1 GiB of Y, 2 GiB per hand-over list
+  // samples per sampling launch (set at creation from free memory, at most
+  // 2^30: 4 GiB of Y and, in step-3 rounds of twice that, 16 GiB per
+  // hand-over list)
+  uint64_t round_max = 1ull << 30;
   RoundSlot slots[2];
   // 1: queue a round whose plan is known before the last is read back; 2:
   // also launch each round as one captured graph; 0: neither
@@ -769,12 +772,15 @@ oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
   HIP_TRY(S.d_pairs.ensure(S.pair_seg.size() * sizeof(PairDesc)));
   HIP_TRY(S.d_res.ensure(words * 8));
   HIP_TRY(S.d_ppart.ensure(oi::pair_sq_blocks(S.ptotal) * 2 * sizeof(unsigned long long)));
-  // the hand-over lists are shared by the queued rounds: growing them waits
-  // for the round in flight
-  if (g->d_def.bytes < total * sizeof(unsigned long long) || g->d_def2.bytes < total * sizeof(unsigned long long))
+  // the round buffer and the hand-over lists are shared by the queued
+  // rounds: growing them waits for the round in flight
+  const size_t ybytes = (S.write_y ? S.off : 0) * sizeof(uint32_t);
+  if (g->d_def.bytes < total * sizeof(unsigned long long) || g->d_def2.bytes < total * sizeof(unsigned long long) ||
+      g->d_y.bytes < ybytes)
     HIP_TRY(hipStreamSynchronize(g->stream));
   HIP_TRY(g->d_def.ensure(total * sizeof(unsigned long long)));
   HIP_TRY(g->d_def2.ensure(total * sizeof(unsigned long long)));
+  if (ybytes) HIP_TRY(g->d_y.ensure(ybytes));
   unsigned long long* res = S.d_res.as<unsigned long long>();
   uint32_t* ydev = g->d_y.as<uint32_t>();
   oi::SampleLaunch A = make_launch(g, S.d_segs.as<oi::Segment>(), S.d_qs.as<oi::QueryDev>(), (int32_t)ns, total,
@@ -922,7 +928,6 @@ oi_status absorb_round(oi_graph* g, std::vector<Rsa>& rs, RoundSlot& S, uint32_t
 // queued before this one is read back, so the GPU does not wait for the host
 // between them.
 oi_status rsa_drive_rounds(oi_graph* g, std::vector<Rsa>& rs, uint32_t seed) {
-  HIP_TRY(g->d_y.ensure((size_t)g->round_max * 4));
   int head = 0, inflight = 0;
   auto retire = [&]() -> oi_status {
     RoundSlot& S = g->slots[head];
@@ -1211,6 +1216,17 @@ oi_status oi_graph_create(int64_t n, int64_t m, const int64_t* row_ptr, const in
   HIP_TRY(g->d_row_ptr.ensure(((size_t)n + 1) * 8));
   HIP_TRY(hipMemcpy(g->d_row_ptr.p, g->row_ptr.data(), ((size_t)n + 1) * 8, hipMemcpyHostToDevice));
   OI_TRY(upload_graph(g.get()));
+  {
+    // rounds as large as a quarter of the free memory allows (36 B per
+    // sample: 4 B of Y, and two 8 B hand-over entries in step-3 rounds of
+    // twice the size), at most 2^30: larger rounds amortise each launch's
+    // tail, where a few deep cascades finish while most of the GPU waits
+    size_t freeb = 0, totalb = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    uint64_t rm = 1ull << 30;
+    while (rm > (1ull << 20) && 36.0 * (double)rm > 0.25 * (double)freeb) rm >>= 1;
+    g->round_max = rm;
+  }
   for (int i = 0; i < 6; ++i) HIP_TRY(hipEventCreate(&g->ev[i]));
   *out = g.release();
   return OI_OK;
