@@ -156,11 +156,13 @@ oi_status oi_estimate_batch(oi_graph* g, int32_t nq, const int64_t* seed_off, co
  * (OI_PARAM_THETA), multiplied by grad_scale.  Each sample is recomputed from
  * its Philox key; y_in (device uint32[count], the forward's Y) may be NULL,
  * in which case the forward is run first.  Accumulation is exact (64-bit
- * integer sums of Y per edge and outcome), finished in fp64 and written as
- * fp32 to grad_out (device float[m]; every entry is written).  The
- * estimator is unbiased for edges with 0 < p_e < 1.  The per-edge sums take
- * 16 bytes per edge of device memory, allocated on the first call and kept
- * by the graph until oi_graph_destroy.
+ * integer sums of Y: per edge over the samples in which it is live, per node
+ * over the samples that expand it, the dead sum of an edge being the
+ * difference), finished in fp64 and written as fp32 to grad_out (device
+ * float[m]; every entry is written).  The estimator is unbiased for edges
+ * with 0 < p_e < 1.  The sums take 8 bytes per edge plus 8 bytes and one
+ * bit per node of device memory, allocated on the first call and kept by the
+ * graph until oi_graph_destroy.
  */
 oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, uint64_t first,
                       uint64_t count, uint32_t run_seed, const uint32_t* y_in, oi_param param, double grad_scale,

@@ -148,6 +148,11 @@ __device__ __forceinline__ bool in_seed_set(const QueryDev& Q, int32_t v) {
   }
 }
 
+// membership in the backward's bitmap of S
+__device__ __forceinline__ bool seed_bit(const uint32_t* sbits, int32_t v) {
+  return (gptr(sbits)[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u;
+}
+
 __device__ __forceinline__ bool in_seed_fields(int32_t k, int32_t s0, uint32_t smask, const int32_t* shash,
                                                int32_t v) {
   if (k == 1) return v == s0;
@@ -433,6 +438,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         qh = 1;
         E = (unsigned long long)(c_re0 - c_rb0);
         if (BWD) atomicAdd(&A.acc_tab[0], (unsigned long long)y);
+        if (BWD && c_re0 > c_rb0) atomicAdd(&A.acc_node[c_v0], (unsigned long long)y);
         if (c_re0 > c_rb0) {
           lo_e = (uint32_t)c_rb0;
           hi_e = (uint32_t)c_re0;
@@ -496,6 +502,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       // iteration (a single-entry start whose node has no out-edges) read
       // nothing; the next iteration finishes it
       if (qh < cnt) {
+        if (BWD && pee > peb) atomicAdd(&A.acc_node[vis[64 * qh]], (unsigned long long)y);
         ++qh;
         E += (unsigned long long)(pee - peb);
         if (pee > peb) {
@@ -566,9 +573,11 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
             }
           } else {
             const bool lv = edge_live(d.w[b], tp[b]);
-            if (BWD || lv) {
+            if (lv) {
               bool ins = tv[b] == s0;
-              if (qk != 1) {
+              if (BWD && A.sbits) {
+                ins = seed_bit(A.sbits, tv[b]);
+              } else if (qk != 1) {
                 uint32_t h = mix32((uint32_t)tv[b]) & smask;
                 while (true) {
                   const int32_t c = gptr(shash)[h];
@@ -584,8 +593,8 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
                 }
               }
               if (!ins) {
-                if (BWD) atomicAdd(lv ? &A.acc_live[x] : &A.acc_dead[x], (unsigned long long)y);
-                if (lv) live |= 1u << b;
+                if (BWD) atomicAdd(&A.acc_live[x], (unsigned long long)y);
+                live |= 1u << b;
               }
             }
           }
@@ -923,8 +932,10 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
       }
     }
     if ((uint32_t)lane < nit) {
-      if (kind == ITEM_NODE && off == 0 && (consumed || take > 0))
+      if (kind == ITEM_NODE && off == 0 && (consumed || take > 0)) {
         atomicAdd(&W.s_E[slot], (unsigned long long)(ee - eb));
+        if (BWD && ee > eb) atomicAdd(&A.acc_node[a], (unsigned long long)W.s_y[slot]);
+      }
       if (consumed) atomicSub(&W.s_pend[slot], 1u);
       if ((uint32_t)lane == cut) {
         // the remainder starts at the first group not taken; a Stage-1 item
@@ -989,10 +1000,9 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
             if (e >= lo_e && e < hi_e) {
               const bool live = edge_live(d.w[b], pa[b]);
               if (BWD) {
-                if (!in_seed_fields(qk, qs0, qmask, qhash, va[b])) {
-                  const unsigned long long y = W.s_y[sl];
-                  atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
-                  if (live && !hash_contains<HCAP>(hs, va[b])) mk |= 1u << b;
+                if (live && !(A.sbits ? seed_bit(A.sbits, va[b]) : in_seed_fields(qk, qs0, qmask, qhash, va[b]))) {
+                  atomicAdd(&A.acc_live[e], (unsigned long long)W.s_y[sl]);
+                  if (!hash_contains<HCAP>(hs, va[b])) mk |= 1u << b;
                 }
               } else if (live && !in_seed_fields(qk, qs0, qmask, qhash, va[b]) &&
                          !hash_contains<HCAP>(hs, va[b])) {
@@ -1291,6 +1301,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
           const int32_t u = queue[head + j];
           rb[k] = (uint32_t)A.row_ptr[u];
           re[k] = (uint32_t)A.row_ptr[u + 1];
+          if (BWD && re[k] > rb[k]) atomicAdd(&A.acc_node[u], y);
         }
       }
 #pragma unroll
@@ -1354,9 +1365,9 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
               const int32_t v = va[u][b];
               if (BWD) {
                 // an edge into S is never revealed (its target is not outside S)
-                if (!in_seed_set(Q, v)) {
-                  atomicAdd(live ? &A.acc_live[e] : &A.acc_dead[e], y);
-                  if (live && claim(bits, v)) push(queue, &s_tail, A.qcap, v);
+                if (live && !(A.sbits ? seed_bit(A.sbits, v) : in_seed_set(Q, v))) {
+                  atomicAdd(&A.acc_live[e], y);
+                  if (claim(bits, v)) push(queue, &s_tail, A.qcap, v);
                 }
               } else if (live && claim(bits, v)) {
                 // S is marked in the bitmap, so a live edge into S claims nothing
@@ -1600,15 +1611,30 @@ __global__ void __launch_bounds__(256) pair_reduce_kernel(const PairSeg* ps, int
 // ---------------------------------------------------------------------------
 // backward finishing: integer Y-sums -> fp32 gradient
 // ---------------------------------------------------------------------------
-// Stage-2 edges: g_p = scale * (L/p - D/(1-p)), g_theta = scale * (L(1-p) - D p).
-__global__ void __launch_bounds__(256) bwd_edges_kernel(const float* pe_arr, int64_t m,
+// Stage-2 edges: g_p = scale * (L/p - D/(1-p)), g_theta = scale * (L(1-p) - D p),
+// with D = N_u - L for an edge (u, v), v outside S (N_u: the Y-sum of the
+// samples that expand u), and L = D = 0 for an edge into S.  One thread per
+// edge; its source u is the row with row_ptr[u] <= e < row_ptr[u + 1], found
+// by binary search (the top levels of which every thread shares, so they
+// stay in cache), which keeps a hub's row spread over many threads.
+__global__ void __launch_bounds__(256) bwd_edges_kernel(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n,
+                                                        int64_t m, const float* pe_arr,
                                                         const unsigned long long* acc_live,
-                                                        const unsigned long long* acc_dead, double scale,
-                                                        int theta, float* grad) {
+                                                        const unsigned long long* acc_node, const uint32_t* sbits,
+                                                        double scale, int theta, float* grad) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
+    int64_t lo = 0, hi = n - 1;  // the first u with row_ptr[u + 1] > e
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (row_ptr[mid + 1] > e)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
     const double p = (double)pe_arr[e];
-    const unsigned long long L = acc_live[e], D = acc_dead[e];
+    const unsigned long long L = acc_live[e];
+    const unsigned long long D = seed_bit(sbits, eg[e >> 2].v[e & 3]) ? 0ull : acc_node[lo] - L;
     double g = 0.0;
     if (theta) {
       g = scale * ((double)L * (1.0 - p) - (double)D * p);
@@ -1853,6 +1879,21 @@ hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, uns
   return hipGetLastError();
 }
 
+// Sets the bit of every seed found in an open-addressing seed-set table of
+// cap entries (empty slots hold -1).
+__global__ void __launch_bounds__(256) seed_bits_kernel(const int32_t* shash, uint32_t cap, uint32_t* sbits) {
+  for (uint32_t h = blockIdx.x * 256u + threadIdx.x; h < cap; h += gridDim.x * 256u) {
+    const int32_t v = shash[h];
+    if (v >= 0) atomicOr(&sbits[(uint32_t)v >> 5], 1u << ((uint32_t)v & 31u));
+  }
+}
+
+hipError_t launch_seed_bits(const int32_t* shash, uint32_t cap, uint32_t* sbits, hipStream_t st) {
+  const uint32_t want = (cap + 255u) / 256u, blocks = want < 64u ? want : 64u;
+  hipLaunchKernelGGL(seed_bits_kernel, dim3(blocks ? blocks : 1u), dim3(256), 0, st, shash, cap, sbits);
+  return hipGetLastError();
+}
+
 __global__ void __launch_bounds__(256) clear_u64_kernel(unsigned long long* p, uint64_t n) {
   for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256) p[i] = 0ull;
 }
@@ -1890,12 +1931,14 @@ hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float
   return hipGetLastError();
 }
 
-hipError_t launch_bwd_edges(const float* pe, int64_t m, const unsigned long long* L,
-                            const unsigned long long* D, double scale, int theta, float* grad, hipStream_t st) {
+hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
+                            const unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
+                            double scale, int theta, float* grad, hipStream_t st) {
   if (m == 0) return hipSuccess;
   int64_t blocks = (m + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, pe, m, L, D, scale, theta, grad);
+  hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row_ptr, eg, n, m, pe, L, N, sbits,
+                     scale, theta, grad);
   return hipGetLastError();
 }
 

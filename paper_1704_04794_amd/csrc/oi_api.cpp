@@ -36,13 +36,15 @@ hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64
                           unsigned long long* part, hipStream_t st);
 uint64_t pair_sq_blocks(uint64_t total);
 hipError_t launch_clear_u64(unsigned long long* p, uint64_t n, hipStream_t st);
+hipError_t launch_seed_bits(const int32_t* shash, uint32_t cap, uint32_t* sbits, hipStream_t st);
 size_t pair_seg_size();
 hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float* p_out, hipStream_t st);
 hipError_t launch_probe_nodes(const EdgeGroup* eg, int64_t m, uint64_t count, uint32_t seed, int32_t* nodes,
                               hipStream_t st);
 hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, const int32_t* nodes, uint64_t count,
                                unsigned long long* out, int cus, hipStream_t st);
-hipError_t launch_bwd_edges(const float* pe, int64_t m, const unsigned long long* L, const unsigned long long* D,
+hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
+                            const unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
                             double scale, int theta, float* grad, hipStream_t st);
 hipError_t launch_bwd_stage1(const float* pe, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
                              const unsigned long long* acc_tab, unsigned long long sumY, double scale, int theta,
@@ -195,7 +197,7 @@ struct oi_graph {
   DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_bits, d_queue;
   // backward workspaces, kept between calls (the per-edge sums are 16 B per
   // edge: allocating them per call cost more than clearing them)
-  DevBuf d_bacc, d_btab, d_bseoff, d_bse, d_bP;
+  DevBuf d_bacc, d_btab, d_bseoff, d_bse, d_bP, d_bsbits;
   int large_blocks = 0;
   uint32_t large_qcap = 0;          // queue entries per large-kernel block
   DevBuf d_gbits, d_gqueue;         // full-size pool for samples that outgrow large_qcap
@@ -331,7 +333,8 @@ oi_status upload_query(oi_graph* g, HostQuery& Q) {
 // ---------------------------------------------------------------------------
 struct BwdBufs {
   const uint32_t* y_in = nullptr;
-  unsigned long long *live = nullptr, *dead = nullptr, *tab = nullptr;
+  unsigned long long *live = nullptr, *node = nullptr, *tab = nullptr;
+  const uint32_t* sbits = nullptr;
 };
 
 // Queue entries per block of the main large-kernel pool: min(n, 2^20).  A
@@ -539,8 +542,9 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   if (is_bwd) {
     A.y_in = bwd->y_in;
     A.acc_live = bwd->live;
-    A.acc_dead = bwd->dead;
+    A.acc_node = bwd->node;
     A.acc_tab = bwd->tab;
+    A.sbits = bwd->sbits;
   }
   OI_TRY(launch_tiers(g, A, is_bwd, g->timing ? g->ev : nullptr, g->stream));
   unsigned long long hctl[16] = {0};
@@ -1415,14 +1419,24 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
   DevBuf& seoff = g->d_bseoff;
   DevBuf& se = g->d_bse;
   DevBuf& P = g->d_bP;
-  HIP_TRY(acc.ensure((size_t)std::max<int64_t>(g->m, 1) * 16));
+  // per edge the live Y-sum, then per node the Y-sum of the samples that expand it
+  const size_t acc_words = (size_t)std::max<int64_t>(g->m, 1) + (size_t)std::max<int64_t>(g->n, 1);
+  HIP_TRY(acc.ensure(acc_words * 8));
   HIP_TRY(tab.ensure((size_t)std::max<int64_t>(Q.l, 1) * 8));
-  HIP_TRY(hipMemsetAsync(acc.p, 0, (size_t)std::max<int64_t>(g->m, 1) * 16, g->stream));
+  HIP_TRY(hipMemsetAsync(acc.p, 0, acc_words * 8, g->stream));
   HIP_TRY(hipMemsetAsync(tab.p, 0, (size_t)std::max<int64_t>(Q.l, 1) * 8, g->stream));
+  // S as an n-bit bitmap, so that the backward's test of every revealed
+  // edge for a target in S is one load
+  DevBuf& sb = g->d_bsbits;
+  const size_t sw = (size_t)((g->n + 31) / 32);
+  HIP_TRY(sb.ensure(sw * 4));
+  HIP_TRY(hipMemsetAsync(sb.p, 0, sw * 4, g->stream));
+  HIP_TRY(oi::launch_seed_bits(Q.dev.shash, Q.smask + 1, sb.as<uint32_t>(), g->stream));
   BwdBufs bb;
   bb.y_in = y;
+  bb.sbits = sb.as<uint32_t>();
   bb.live = acc.as<unsigned long long>();
-  bb.dead = acc.as<unsigned long long>() + std::max<int64_t>(g->m, 1);
+  bb.node = acc.as<unsigned long long>() + std::max<int64_t>(g->m, 1);
   bb.tab = tab.as<unsigned long long>();
   std::vector<SegReq> seg{{0, 0, first, count, 0}};
   std::vector<unsigned long long> s;
@@ -1438,8 +1452,8 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
     if (g->m) HIP_TRY(hipMemcpy(g->d_p.p, g->p.data(), (size_t)g->m * sizeof(float), hipMemcpyHostToDevice));
     g->d_p_ok = true;
   }
-  HIP_TRY(oi::launch_bwd_edges(g->d_p.as<float>(), g->m, bb.live, bb.dead, scale, theta, grad_out,
-                               g->stream));
+  HIP_TRY(oi::launch_bwd_edges(g->d_row_ptr.as<int64_t>(), g->d_eg.as<oi::EdgeGroup>(), g->n, g->m,
+                               g->d_p.as<float>(), bb.live, bb.node, bb.sbits, scale, theta, grad_out, g->stream));
   HIP_TRY(seoff.ensure(Q.se_off.size() * 8));
   HIP_TRY(se.ensure(std::max<size_t>(Q.se.size(), 1) * 8));
   HIP_TRY(P.ensure(std::max<size_t>(Q.P.size(), 1) * 8));

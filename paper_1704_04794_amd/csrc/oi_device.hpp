@@ -108,8 +108,15 @@ struct SampleLaunch {
   // backward accumulators (null in the forward)
   const uint32_t* y_in;            // per-sample Y from the forward
   unsigned long long* acc_live;    // per edge: sum of Y over samples where the edge is revealed live
-  unsigned long long* acc_dead;    // per edge: ... revealed dead
+  // per node u: sum of Y over samples that expand u.  Every out-edge of an
+  // expanded node is revealed unless its target is in S, so an edge's
+  // "revealed dead" sum is acc_node[u] - acc_live[e]: one atomic per
+  // expanded node instead of one per dead edge
+  unsigned long long* acc_node;
   unsigned long long* acc_tab;     // per Stage-1 entry: sum of Y over samples with x_j = 1
+  // backward: S as an n-bit bitmap (one load per membership test instead
+  // of a probe of the seed-set hash), or null
+  const uint32_t* sbits;
 };
 
 // Hash used for the per-query seed set table (built on the host, probed on the device).
