@@ -234,19 +234,37 @@ def batched_vs_single(P, args):
     delta = extra["delta"]
     G = P.Graph.from_inputs(g)
     G.estimate(sub[0], 0.5, delta, query_id=int(qids[0]))  # warm up kernels and workspaces
-    t = time.perf_counter()
-    tune = G.autotune(sub, pilot=4096, query_ids=qids)
-    log(f"autotune ({time.perf_counter() - t:.1f}s): {tune}")
+    tune = None
+    if not args.no_autotune:
+        t = time.perf_counter()
+        tune = G.autotune(sub, pilot=4096, query_ids=qids)
+        log(f"autotune ({time.perf_counter() - t:.1f}s): {tune}")
+    probe = gather_roofline(G)
     import torch
     torch.cuda.synchronize()
+    # both passes with HIP-event kernel timing on (same cost for both)
+    G.timing(True)
     t = time.perf_counter()
     batch = G.estimate_batch(sub, eps, delta, query_ids=qids)
     tb = time.perf_counter() - t
+    tm = G.timing()
     log(f"batched: {len(sub)} sets in {tb:.2f}s")
+    G.timing(True)
     t = time.perf_counter()
     single = [G.estimate(S, eps, delta, query_id=int(q)) for S, q in zip(sub, qids)]
     ts = time.perf_counter() - t
+    G.timing(False)
     log(f"one at a time: {len(sub)} sets in {ts:.2f}s")
+    # the large-cascade kernel of the batched pass against the random-read
+    # roofline: algorithmic bytes of the samples it finished over its time
+    kbytes = BYTES_PER_NODE * tm["large_y"] + BYTES_PER_EDGE * tm["large_edges"]
+    kgbps = kbytes / (tm["large_ms"] * 1e-3) / 1e9 if tm["large_ms"] > 0 else 0.0
+    large = {"kernel": "large_kernel", "ms": tm["large_ms"], "launches": tm["launches"],
+             "activated": tm["large_y"], "edges": tm["large_edges"],
+             "gteps": tm["large_edges"] / (tm["large_ms"] * 1e-3) / 1e9 if tm["large_ms"] > 0 else 0.0,
+             "achieved_gbps": kgbps, "frac_of_hbm_peak": kgbps / HBM_PEAK_GBS,
+             "gather_probe_gbps": probe["gbps"], "frac_of_measured_gather": kgbps / probe["gbps"],
+             "share_of_batched_time": tm["large_ms"] * 1e-3 / tb}
     same = all(a["oi"] == b["oi"] and a["T"] == b["T"] for a, b in zip(batch, single))
     samples = sum(r["samples_x"] + r["samples_xp"] for r in batch)
     G.close()
@@ -255,7 +273,7 @@ def batched_vs_single(P, args):
             f"({k} uniform + {k} top-1% out-degree, |S| in [1,1000]), SOIEA eps={eps} delta={delta}",
             "batched_estimates_per_s": len(sub) / tb, "single_estimates_per_s": len(sub) / ts,
             "speedup": ts / tb, "identical_results": same, "samples": samples,
-            "batched_samples_per_s": samples / tb, "autotune": tune}
+            "batched_samples_per_s": samples / tb, "large_kernel": large, "autotune": tune}
 
 
 def main():
@@ -273,6 +291,7 @@ def main():
                     help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time; "
                          "cl100m: the billion-edge graph")
     ap.add_argument("--queries", type=int, default=32, help="cl4m: number of seed sets in the subset")
+    ap.add_argument("--no-autotune", action="store_true", help="cl4m: keep the default sampler schedule")
     ap.add_argument("--eps", type=float, default=-1.0, help="cl4m: eps (default: the workload's 0.1)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device with torch (a plain copy kernel of known size, "
@@ -292,12 +311,6 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    if args.workload == "cl4m":
-        print(json.dumps(batched_vs_single(P, args)), flush=True)
-        return
-    if args.workload == "cl100m":
-        print(json.dumps(billion_edge(P, args)), flush=True)
-        return
     if args.copy_calibration:
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -305,6 +318,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
         log("copied 1 GiB device-to-device for counter calibration")
+    if args.workload == "cl4m":
+        print(json.dumps(batched_vs_single(P, args)), flush=True)
+        return
+    if args.workload == "cl100m":
+        print(json.dumps(billion_edge(P, args)), flush=True)
+        return
     t = time.perf_counter()
     g, sets, extra = make_config("cl1m")
     S = sets[0]

@@ -195,8 +195,8 @@ struct oi_graph {
   bool d_p_ok = false;
   // per-launch workspaces
   DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_bits, d_queue;
-  // backward workspaces, kept between calls (the per-edge sums are 16 B per
-  // edge: allocating them per call cost more than clearing them)
+  // backward workspaces, kept between calls (the per-edge and per-node sums
+  // are 8 B each: allocating them per call cost more than clearing them)
   DevBuf d_bacc, d_btab, d_bseoff, d_bse, d_bP, d_bsbits;
   int large_blocks = 0;
   uint32_t large_qcap = 0;          // queue entries per large-kernel block
