@@ -43,6 +43,15 @@ def _rel_l2(a, b):
     return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
 
 
+def _per_edge(a, b):
+    """Every edge on its own: the GPU's per-edge and per-node Y-sums are exact
+    integers, so each gradient entry differs from the fp64 oracle's only by
+    the final fp32 rounding and the oracle's own summation order."""
+    tol = 1e-6 * np.abs(b) + 1e-7 * np.abs(b).max()
+    bad = np.flatnonzero(np.abs(a - b) > tol)
+    assert bad.size == 0, (bad[:8], a[bad[:8]], b[bad[:8]])
+
+
 def test_tiny16_matches_oracle_and_enumeration(P):
     g = tiny16_graph()
     G = P.Graph.from_inputs(g)
@@ -52,6 +61,7 @@ def test_tiny16_matches_oracle_and_enumeration(P):
         gg = _gpu_grad(P, G, S, N, qid=len(S))
         og, se = _oracle_grad(g, S, N, qid=len(S), sq=True)
         assert _rel_l2(gg, og) <= REL_L2, _rel_l2(gg, og)
+        _per_edge(gg, og)
         ex = O.exact(g, S, want_grad=True)["grad"]
         live = np.abs(ex) > 1e-12
         assert np.all(np.abs(gg[live] - ex[live]) < 4 * se[live] + 1e-7)
@@ -105,6 +115,7 @@ def test_forward_y_reused_and_large_samples(P):
     np.testing.assert_array_equal(a, b)
     og, _ = _oracle_grad(gw, S, N)
     assert _rel_l2(a, og) <= REL_L2
+    _per_edge(a, og)
     G.close()
 
 
@@ -129,6 +140,7 @@ def test_cl1m_sigmoid_workload(P):
     gg = _gpu_grad(P, G, S, N, param=P.OI_PARAM_P)
     og, _ = _oracle_grad(g, S, N)
     assert _rel_l2(gg, og) <= REL_L2, _rel_l2(gg, og)
+    _per_edge(gg, og)
     G.close()
 
 
