@@ -38,8 +38,8 @@ BYTES_PER_EDGE = 8   # col (int32) + coin threshold (uint32) per examined edge
 # 1 GiB device copy gives those counters), mean over the 7 launches of one
 # estimate.  Reported only while the kernel sources (their code, comments
 # aside) hash to what was measured and an estimate takes as many launches.
-TRAFFIC = {"sources_sha1": "d7904624e98b3651278512edb2892ece85e817cf", "kernel": "tiny_kernel",
-           "launches_per_estimate": 7, "bytes_per_launch": 2563518464.0, "l2_hit_rate": 0.785}
+TRAFFIC = {"sources_sha1": "7f666df65be25dbb4969b8c5a52e3bf1a41cea37", "kernel": "tiny_kernel",
+           "launches_per_estimate": 7, "bytes_per_launch": 2563906560.0, "l2_hit_rate": 0.785}
 KERNEL_SOURCES = ("paper_1704_04794_amd/csrc/iicp_kernels.hip", "paper_1704_04794_amd/csrc/oi_device.hpp")
 
 
@@ -164,7 +164,9 @@ def billion_edge(P, args):
            "build_s": build_s, "upload_s": upload_s, "gather_probe_gbps": probe["gbps"], "fixed": []}
     for qi, N in ((0, 1 << 26), (1, 1 << 20), (2, 1 << 15)):
         S = sets[qi]
-        G.sample_fixed(S, 4096, query_id=qi)
+        # a warm-up of the same size: the large kernel's queue cap adapts to
+        # what the previous launch saw
+        G.sample_fixed(S, N, query_id=qi)
         G.timing(True)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -173,7 +175,8 @@ def billion_edge(P, args):
         dt = time.perf_counter() - t
         tm = G.timing()
         row = {"k": int(len(S)), "query": qi, "samples": N, "seconds": dt, "samples_per_s": N / dt,
-               "gteps": r["edges_examined"] / dt / 1e9, "y_mean": r["sum_y"] / N, "beta0": r["beta0"],
+               "gteps": r["edges_examined"] / dt / 1e9, "sum_y": r["sum_y"], "y_mean": r["sum_y"] / N,
+               "beta0": r["beta0"],
                "kernel_ms": {k: tm[f"{k}_ms"] for k in ("tiny", "small", "large")}}
         out["fixed"].append(row)
         log(f"fixed |S|={len(S)}: {row}")
@@ -188,6 +191,27 @@ def billion_edge(P, args):
                             "oi": r["oi"], "samples": r["samples_x"] + r["samples_xp"], "rounds": r["rounds"],
                             "samples_per_s": (r["samples_x"] + r["samples_xp"]) / dt}
     log(f"SIEA estimate: {out['siea_estimate']}")
+    # the same two runs with the large kernel's queue cap fixed at 2^20 (no
+    # adaptation): the rare giant cascades then keep one 256-thread block
+    # busy long after the rest of a launch has finished (results identical)
+    G.tune(large_qcap=1 << 20)
+    S = sets[0]
+    G.sample_fixed(S, 1 << 26, query_id=0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    _, _, rq = G.sample_fixed(S, 1 << 26, query_id=0)
+    torch.cuda.synchronize()
+    tq = time.perf_counter() - t
+    t = time.perf_counter()
+    rs = G.estimate(S, 0.1, 1.0 / g.n, mode=P.OI_MODE_SIEA, query_id=0)
+    dt = time.perf_counter() - t
+    out["fixed_queue_cap_2e20"] = {"fixed_k1_seconds": tq, "fixed_k1_samples_per_s": (1 << 26) / tq,
+                                   "siea_seconds": dt,
+                                   "siea_samples_per_s": (rs["samples_x"] + rs["samples_xp"]) / dt,
+                                   "identical": rq["sum_y"] == out["fixed"][0]["sum_y"] and rs["is_"] == r["is_"]
+                                   and rs["T"] == r["T"]}
+    log(f"queue cap fixed at 2^20: {out['fixed_queue_cap_2e20']}")
+    G.tune(large_qcap=0)
     S = sets[2]
     N = 1 << 14
     grad = torch.empty(g.m, dtype=torch.float32, device="cuda")

@@ -120,7 +120,7 @@ class Graph:
     def tune(self, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1, small_direct=-1, large_qcap=-1,
              pipeline=None):
         oi_set_tuning(self.h, variant, chunk, tiny, tiny_chunk, round_max)
-        if small_direct >= 0 or large_qcap > 0:
+        if small_direct >= 0 or large_qcap >= 0:
             oi_set_routing(self.h, small_direct, large_qcap)
         if pipeline is not None:
             oi_set_pipeline(self.h, pipeline)

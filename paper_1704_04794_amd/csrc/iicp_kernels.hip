@@ -1401,6 +1401,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       } else {
         if (A.y_out) A.y_out[oidx] = Y;
         if (A.e_out) A.e_out[oidx] = s_E;
+        if (A.nbig && Y > A.big_mark) atomicAdd(A.nbig, 1u);
       }
       atomicAdd(&A.seg_sums[2 * sg], (unsigned long long)Y);
       atomicAdd(&A.seg_sums[2 * sg + 1], s_E);

@@ -204,6 +204,7 @@ struct oi_graph {
   int giant_blocks = 0;
   int small_direct = 0;             // 0: automatic, 1: always, 2: never (see oi_set_routing)
   int64_t qcap_override = 0;        // > 0: queue entries per main-pool block
+  uint32_t qcap_eff = 0;            // the cap launches use (<= large_qcap; 0: large_qcap)
   int variant = 0;
   bool use_tiny = true;
   uint32_t chunk = 256;
@@ -341,6 +342,11 @@ struct BwdBufs {
 // sample that activates more nodes goes to a second pass over blocks with
 // n-entry queues, so the main pool can hold many blocks even for n = 1e8.
 constexpr int64_t kLargeQcap = 1 << 20;
+// blocks of the full-queue pass (at most)
+constexpr int kGiantBlocksMax = 64;
+// activations above which a sample counts as giant for the adaptive cap:
+// 2^17, or an eighth of the pool's cap on graphs too small for that
+constexpr uint32_t kBigMark = 1u << 17;
 
 oi_status ensure_large_pool(oi_graph* g) {
   if (g->large_blocks > 0) return OI_OK;
@@ -364,6 +370,7 @@ oi_status ensure_large_pool(oi_graph* g) {
   HIP_TRY(hipStreamSynchronize(g->stream));
   g->large_blocks = blocks;
   g->large_qcap = (uint32_t)qcap;
+  g->qcap_eff = 0;
   return OI_OK;
 }
 
@@ -377,7 +384,7 @@ oi_status ensure_giant_pool(oi_graph* g) {
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
   const double budget = std::min(32.0 * (1ull << 30), 0.25 * (double)freeb);
-  int blocks = (int)std::min<double>(64.0, std::floor(budget / per));
+  int blocks = (int)std::min<double>((double)kGiantBlocksMax, std::floor(budget / per));
   if (blocks < 1) return fail(OI_ENOMEM, "no room for a full-size cascade workspace");
   HIP_TRY(g->d_gbits.ensure((size_t)blocks * (size_t)words * 4));
   HIP_TRY(g->d_gqueue.ensure((size_t)blocks * (size_t)g->n * 4));
@@ -387,10 +394,42 @@ oi_status ensure_giant_pool(oi_graph* g) {
   return OI_OK;
 }
 
+// The main pool's queue cap for the next launches.  A launch lasts as long
+// as its largest sample.  When only a few samples of a launch activate more
+// than big_mark nodes (the rare giant cascades of a huge sparse graph), a
+// cap of big_mark sends them early to the full-queue pass, whose 1024-thread
+// blocks finish them side by side, instead of leaving one 256-thread block
+// each running long after the rest of the launch; when many do (a graph
+// where most samples are that large), the full-queue pass would be the
+// bottleneck and the cap stays at the pool's size.  Decided from the
+// previous forward launch's count; results never depend on the cap.  A cap
+// set by oi_set_routing is kept as set.
+uint32_t big_mark(const oi_graph* g) { return std::min<uint32_t>(kBigMark, g->large_qcap / 8); }
+
+oi_status adapt_qcap(oi_graph* g, const unsigned long long* ctl) {
+  const uint32_t mark = big_mark(g);
+  if (g->qcap_override > 0 || mark == 0) return OI_OK;
+  const uint64_t big = (ctl[14] & 0xffffffffull) + (ctl[12] & 0xffffffffull);
+  if (big == 0) return OI_OK;  // no evidence either way
+  const uint64_t room = g->giant_blocks > 0 ? (uint64_t)g->giant_blocks : (uint64_t)kGiantBlocksMax;
+  if (big <= room) {
+    if (g->qcap_eff != mark) {
+      // overflowing samples need the full-queue pool in place before a
+      // round is queued with the lower cap
+      OI_TRY(ensure_giant_pool(g));
+      if (big <= (uint64_t)g->giant_blocks) g->qcap_eff = mark;
+    }
+  } else {
+    g->qcap_eff = 0;
+  }
+  return OI_OK;
+}
+
 // Launch arguments shared by every sampling launch.  ctl is the 16-word
 // control block:
 //   [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier
-//   sums, [11] counter2, [12] nlist3, [13] the full-queue pass's counter
+//   sums, [11] counter2, [12] nlist3, [13] the full-queue pass's counter,
+//   [14] samples the large kernel finished with more than big_mark activations
 // and sums holds (sum Y, sum E) per segment.
 oi::SampleLaunch make_launch(const oi_graph* g, const oi::Segment* d_segs, const oi::QueryDev* d_qs, int32_t nseg,
                              uint64_t total, uint32_t seed, uint32_t* y_dev, uint64_t* e_dev,
@@ -423,8 +462,10 @@ oi::SampleLaunch make_launch(const oi_graph* g, const oi::Segment* d_segs, const
   A.bits = g->d_bits.as<uint32_t>();
   A.queue = g->d_queue.as<int32_t>();
   A.bits_words = (g->n + 31) / 32;
-  A.qcap = g->large_qcap;
+  A.qcap = g->qcap_eff ? g->qcap_eff : g->large_qcap;
   A.queue_stride = (int64_t)g->large_qcap;
+  A.nbig = reinterpret_cast<unsigned int*>(ctl + 14);
+  A.big_mark = big_mark(g);
   // list1's storage is free once the small kernel has run: it holds list3
   A.list3 = g->d_def.as<unsigned long long>();
   A.nlist3 = reinterpret_cast<unsigned int*>(ctl + 12);
@@ -444,6 +485,7 @@ oi::SampleLaunch make_giant_launch(const oi_graph* g, const oi::SampleLaunch& A,
   B.queue_stride = g->n;
   B.list3 = nullptr;
   B.nlist3 = nullptr;
+  B.nbig = nullptr;  // its samples are already counted in nlist3
   return B;
 }
 
@@ -568,6 +610,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   HIP_TRY(hipStreamSynchronize(g->stream));
   const unsigned int err = (unsigned int)(hctl[4] & 0xffffffffull);
   if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
+  if (!is_bwd) OI_TRY(adapt_qcap(g, hctl));
   if (rounds) ++*rounds;
   if (g->timing) {
     float t0 = 0, t1 = 0, t2 = 0;
@@ -867,6 +910,7 @@ oi_status wait_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
   }
   const unsigned int err = (unsigned int)(res[4] & 0xffffffffull);
   if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
+  OI_TRY(adapt_qcap(g, res));
   if (S.timed) {
     float t0 = 0, t1 = 0, t2 = 0, t3 = 0;
     OI_TRY(elapsed(S.ev[0], S.ev[1], &t0));
@@ -1585,9 +1629,9 @@ oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap) {
   if (!g) return fail(OI_EINVAL, "null graph");
   if (small_direct > 2) return fail(OI_EINVAL, "small_direct must be -1, 0, 1 or 2");
   if (small_direct >= 0) g->small_direct = small_direct;
-  if (large_qcap > 0 && large_qcap != g->qcap_override) {
+  if (large_qcap >= 0 && large_qcap != g->qcap_override) {
     HIP_TRY(hipStreamSynchronize(g->stream));
-    g->qcap_override = large_qcap;
+    g->qcap_override = large_qcap;  // 0: the default, adaptive cap
     g->d_bits.release();
     g->d_queue.release();
     g->large_blocks = 0;

@@ -117,6 +117,11 @@ struct SampleLaunch {
   // backward: S as an n-bit bitmap (one load per membership test instead
   // of a probe of the seed-set hash), or null
   const uint32_t* sbits;
+  // the large kernel counts the samples it finishes with more than big_mark
+  // activations (null: no count); the host sizes the next launch's queue
+  // cap from it
+  unsigned int* nbig;
+  uint32_t big_mark;
 };
 
 // Hash used for the per-query seed set table (built on the host, probed on the device).
