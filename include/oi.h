@@ -204,16 +204,17 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
  * large kernel when there are no more of them than large-kernel blocks; 1
  * always forwards them (the small kernel does no sampling); 2 never does;
  * -1 keeps the setting.  The large kernel's main pool has queues of
- * min(n, 2^20) entries per block; a sample that activates more nodes than a
- * launch's cap is finished by a second pass with n-entry queues and
- * 1024-thread blocks.  By default (large_qcap = 0) the cap adapts: after a
- * launch in which only a few samples (no more than the second pass has
- * blocks) activated more than min(2^17, pool entries / 8) nodes, the next
- * launches use that lower cap, so such rare giant samples leave the main
- * pool early and finish side by side instead of keeping one 256-thread block
- * busy long after the rest of the launch; after a launch with more of them,
- * the cap returns to the pool's size.  large_qcap > 0 fixes the cap (and the
- * pool's queues) at that many entries, with no adaptation.  Changing
+ * min(n, 2^20) entries per block; a sample that activates more nodes than
+ * that is finished by a second pass with n-entry queues and 1024-thread
+ * blocks.  By default (large_qcap = 0) a soft cap adapts: after a launch in
+ * which only a few samples (at most four per block of the second pass)
+ * activated more than min(2^17, queue entries / 8) nodes, such samples of
+ * the next launches leave the main pool once they pass that mark (at most
+ * two per second-pass block per launch; later ones go on in the main pool),
+ * so rare giant samples finish side by side in the second pass instead of
+ * keeping one 256-thread block busy long after the rest of the launch;
+ * after a launch with more of them the soft cap is lifted.  large_qcap > 0
+ * fixes the queues at that many entries, with no soft cap.  Changing
  * large_qcap reallocates the pool.  Results do not depend on either
  * setting.  Errors: OI_EINVAL for a null graph or small_direct > 2. */
 oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);

@@ -1217,6 +1217,7 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
   __shared__ uint32_t it_ee[NT * LBN];
   __shared__ int64_t s_i;
   __shared__ uint32_t s_di;
+  __shared__ uint32_t s_go;
   const int tid = threadIdx.x;
   uint32_t* bits = A.bits + (int64_t)blockIdx.x * A.bits_words;
   int32_t* queue = A.queue + (int64_t)blockIdx.x * A.queue_stride;
@@ -1285,9 +1286,23 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
     // nodes, LBN consecutive queue entries per thread (their row reads are
     // independent, so they are in flight together)
     uint32_t head = 0;
+    // the soft cap (block-uniform): a forward sample that grows past it
+    // leaves for the full-queue pass while this launch's budget of such
+    // departures lasts, and otherwise goes on up to the queue's size
+    uint32_t cap = BWD ? A.qcap : A.soft_cap;
+    bool leave = false;
     while (true) {
       const uint32_t tail = s_tail;
       __syncthreads();
+      if (!BWD && tail > cap && cap < A.qcap) {
+        if (tid == 0) s_go = atomicAdd(A.nsoft, 1u) < A.soft_budget ? 1u : 0u;
+        __syncthreads();
+        if (s_go) {
+          leave = true;
+          break;
+        }
+        cap = A.qcap;
+      }
       if (head >= tail || tail > A.qcap) break;
       const uint32_t nb = tail - head < (uint32_t)(NT * LBN) ? tail - head : (uint32_t)(NT * LBN);
       uint32_t rb[LBN], re[LBN], part[LBN];
@@ -1381,10 +1396,11 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       __syncthreads();
     }
     const uint32_t Y = s_tail;
-    if (Y > A.qcap) {
-      // outgrew the queue: nothing of the sample was recorded; it goes to
-      // the pass with full-size queues, and the whole bitmap is cleared
-      // (bits were set for nodes the queue could not hold)
+    if (leave || Y > A.qcap) {
+      // outgrew the queue (or left at the soft cap): nothing of the sample
+      // was recorded; it goes to the pass with full-size queues, and the
+      // whole bitmap is cleared (bits may be set for nodes the queue could
+      // not hold)
       if (tid == 0) {
         if (!BWD && A.list3)
           A.list3[atomicAdd(A.nlist3, 1u)] = f;

@@ -204,7 +204,7 @@ struct oi_graph {
   int giant_blocks = 0;
   int small_direct = 0;             // 0: automatic, 1: always, 2: never (see oi_set_routing)
   int64_t qcap_override = 0;        // > 0: queue entries per main-pool block
-  uint32_t qcap_eff = 0;            // the cap launches use (<= large_qcap; 0: large_qcap)
+  uint32_t qcap_eff = 0;            // the large kernel's soft cap (<= large_qcap; 0: large_qcap)
   int variant = 0;
   bool use_tiny = true;
   uint32_t chunk = 256;
@@ -394,16 +394,19 @@ oi_status ensure_giant_pool(oi_graph* g) {
   return OI_OK;
 }
 
-// The main pool's queue cap for the next launches.  A launch lasts as long
-// as its largest sample.  When only a few samples of a launch activate more
-// than big_mark nodes (the rare giant cascades of a huge sparse graph), a
-// cap of big_mark sends them early to the full-queue pass, whose 1024-thread
-// blocks finish them side by side, instead of leaving one 256-thread block
-// each running long after the rest of the launch; when many do (a graph
-// where most samples are that large), the full-queue pass would be the
-// bottleneck and the cap stays at the pool's size.  Decided from the
-// previous forward launch's count; results never depend on the cap.  A cap
-// set by oi_set_routing is kept as set.
+// The large kernel's soft cap for the next launches.  A launch lasts as
+// long as its largest sample.  When a launch saw only a few samples with
+// more than big_mark activations (the rare giant cascades of a huge sparse
+// graph: at most four per block of the full-queue pass), the next launches
+// let such samples leave the main pool once they pass big_mark, for the
+// full-queue pass, whose 1024-thread blocks finish them side by side,
+// instead of each keeping one 256-thread block running long after the rest
+// of the launch.  At most two per full-queue block leave per launch (the
+// kernel's budget), so a launch with more of them than expected costs at
+// most two waves of that pass; after a launch with many of them (a graph
+// where most samples are that large) the soft cap is lifted again.
+// Decided from the previous forward launch; results never depend on it.  A
+// cap set by oi_set_routing is kept as set.
 uint32_t big_mark(const oi_graph* g) { return std::min<uint32_t>(kBigMark, g->large_qcap / 8); }
 
 oi_status adapt_qcap(oi_graph* g, const unsigned long long* ctl) {
@@ -412,12 +415,12 @@ oi_status adapt_qcap(oi_graph* g, const unsigned long long* ctl) {
   const uint64_t big = (ctl[14] & 0xffffffffull) + (ctl[12] & 0xffffffffull);
   if (big == 0) return OI_OK;  // no evidence either way
   const uint64_t room = g->giant_blocks > 0 ? (uint64_t)g->giant_blocks : (uint64_t)kGiantBlocksMax;
-  if (big <= room) {
+  if (big <= 4 * room) {
     if (g->qcap_eff != mark) {
-      // overflowing samples need the full-queue pool in place before a
-      // round is queued with the lower cap
+      // samples that leave need the full-queue pool in place before a
+      // round is queued with the soft cap
       OI_TRY(ensure_giant_pool(g));
-      if (big <= (uint64_t)g->giant_blocks) g->qcap_eff = mark;
+      g->qcap_eff = mark;
     }
   } else {
     g->qcap_eff = 0;
@@ -429,7 +432,8 @@ oi_status adapt_qcap(oi_graph* g, const unsigned long long* ctl) {
 // control block:
 //   [0] counter, [1] counter1, [2] nlist1, [3] nlist2, [4] err, [5..10] tier
 //   sums, [11] counter2, [12] nlist3, [13] the full-queue pass's counter,
-//   [14] samples the large kernel finished with more than big_mark activations
+//   [14] samples the large kernel finished with more than big_mark activations,
+//   [15] samples that left the main pool at the soft cap
 // and sums holds (sum Y, sum E) per segment.
 oi::SampleLaunch make_launch(const oi_graph* g, const oi::Segment* d_segs, const oi::QueryDev* d_qs, int32_t nseg,
                              uint64_t total, uint32_t seed, uint32_t* y_dev, uint64_t* e_dev,
@@ -462,10 +466,13 @@ oi::SampleLaunch make_launch(const oi_graph* g, const oi::Segment* d_segs, const
   A.bits = g->d_bits.as<uint32_t>();
   A.queue = g->d_queue.as<int32_t>();
   A.bits_words = (g->n + 31) / 32;
-  A.qcap = g->qcap_eff ? g->qcap_eff : g->large_qcap;
+  A.qcap = g->large_qcap;
   A.queue_stride = (int64_t)g->large_qcap;
   A.nbig = reinterpret_cast<unsigned int*>(ctl + 14);
   A.big_mark = big_mark(g);
+  A.soft_cap = g->qcap_eff ? g->qcap_eff : g->large_qcap;
+  A.soft_budget = 2u * (uint32_t)(g->giant_blocks > 0 ? g->giant_blocks : kGiantBlocksMax);
+  A.nsoft = reinterpret_cast<unsigned int*>(ctl + 15);
   // list1's storage is free once the small kernel has run: it holds list3
   A.list3 = g->d_def.as<unsigned long long>();
   A.nlist3 = reinterpret_cast<unsigned int*>(ctl + 12);
@@ -486,6 +493,8 @@ oi::SampleLaunch make_giant_launch(const oi_graph* g, const oi::SampleLaunch& A,
   B.list3 = nullptr;
   B.nlist3 = nullptr;
   B.nbig = nullptr;  // its samples are already counted in nlist3
+  B.soft_cap = B.qcap;
+  B.nsoft = nullptr;
   return B;
 }
 

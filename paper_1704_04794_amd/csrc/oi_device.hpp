@@ -118,10 +118,17 @@ struct SampleLaunch {
   // of a probe of the seed-set hash), or null
   const uint32_t* sbits;
   // the large kernel counts the samples it finishes with more than big_mark
-  // activations (null: no count); the host sizes the next launch's queue
-  // cap from it
+  // activations (null: no count); the host sets the next launch's soft cap
+  // from it
   unsigned int* nbig;
   uint32_t big_mark;
+  // forward large kernel: a sample that activates more than soft_cap (<=
+  // qcap) nodes leaves for the full-queue pass if fewer than soft_budget
+  // samples of the launch have left that way (counted in nsoft), and
+  // otherwise continues up to qcap; soft_cap == qcap turns this off
+  uint32_t soft_cap;
+  uint32_t soft_budget;
+  unsigned int* nsoft;
 };
 
 // Hash used for the per-query seed set table (built on the host, probed on the device).
