@@ -180,7 +180,9 @@ typedef struct {
   uint64_t handed_large;              /* samples passed from small to large */
   uint64_t tiny_y, tiny_edges;        /* sum of Y and examined edges of the samples each kernel finished */
   uint64_t small_y, small_edges;
-  uint64_t large_y, large_edges;
+  uint64_t large_y, large_edges;      /* (the large kernel's figures include its full-queue pass) */
+  uint64_t handed_full;               /* samples passed to the large kernel's full-queue pass */
+  uint64_t left_soft;                 /* ... of which left the main pool at the soft cap */
 } oi_timing;
 
 /* enable != 0 turns event timing on (and resets the counters). */

@@ -53,7 +53,7 @@ class oi_timing(C.Structure):
         ("launches", C.c_uint64), ("samples", C.c_uint64), ("handed_small", C.c_uint64),
         ("handed_large", C.c_uint64), ("tiny_y", C.c_uint64), ("tiny_edges", C.c_uint64),
         ("small_y", C.c_uint64), ("small_edges", C.c_uint64), ("large_y", C.c_uint64),
-        ("large_edges", C.c_uint64),
+        ("large_edges", C.c_uint64), ("handed_full", C.c_uint64), ("left_soft", C.c_uint64),
     ]
 
     def as_dict(self):

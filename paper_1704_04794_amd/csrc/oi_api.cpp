@@ -545,6 +545,10 @@ void add_timing(oi_graph* g, const unsigned long long* hctl, uint64_t total, flo
   g->tm.small_edges += hctl[8];
   g->tm.large_y += hctl[9];
   g->tm.large_edges += hctl[10];
+  g->tm.handed_full += hctl[12] & 0xffffffffull;
+  // every sample that passed the soft cap took a ticket; those within the
+  // budget (two per full-queue block) left
+  g->tm.left_soft += std::min<uint64_t>(hctl[15] & 0xffffffffull, 2ull * (uint64_t)std::max(g->giant_blocks, 0));
 }
 
 oi_status elapsed(hipEvent_t a, hipEvent_t b, float* ms) {

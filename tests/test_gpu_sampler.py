@@ -208,6 +208,39 @@ def test_few_handed_samples_go_straight_to_the_large_kernel(P):
     G.close()
 
 
+def test_soft_cap_departures_bit_exact(P):
+    """The large kernel's adaptive soft cap.  On this graph its mark is an
+    eighth of the pool's queues (2,500 activations) and 52 of the first
+    20,000 samples of this seed set pass it: after the first launch has
+    counted them, the next launch sends such samples to the full-queue pass
+    once they pass the mark.  Per-sample Y and E stay bit-exact with the
+    oracle, and so do an RSA estimate and the backward run after it."""
+    import torch
+    g = chung_lu_graph(20000, 200000, 2.1, 7)
+    gw = g.with_p(wc_probs(g))
+    S = uniform_seed_set(gw, 5, 2)
+    G = _gpu_graph(P, gw)
+    G.timing(True)
+    _compare(P, gw, S, 20000, G=G, label="cl20k wc soft cap, first launch")
+    t = G.timing()
+    assert t["left_soft"] == 0, t
+    G.timing(True)
+    _compare(P, gw, S, 20000, G=G, label="cl20k wc soft cap, second launch")
+    t = G.timing()
+    assert 0 < t["left_soft"] <= t["handed_full"], t
+    a = G.estimate(S, 0.2, 1e-2, mode=0, query_id=0)
+    b = O.estimate(gw, S, 0.2, 1e-2, 0, 0, RUN_SEED)
+    assert a["oi"] == b["oi"] and a["T"] == b["rsa"]["T"] and a["D"] == b["rsa"]["D"]
+    N = 20000
+    grad = torch.empty(gw.m, dtype=torch.float32, device="cuda")
+    G.backward(S, N, grad)
+    o = O.backward(gw, S, 0, RUN_SEED, 0, N)
+    ref = o["beta0"] * o["acc"] / N
+    got = grad.cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    G.close()
+
+
 @pytest.mark.parametrize("small_direct,qcap", [(1, 24), (2, 24), (0, 1 << 20)])
 def test_routing_and_capped_queues_bit_exact(P, small_direct, qcap):
     """Routing settings do not change results: hand-overs forced through or
