@@ -595,6 +595,10 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
                                    total, seed, y_dev, e_dev, ctl, g->d_sums.as<unsigned long long>());
   const bool is_bwd = bwd != nullptr;
   if (is_bwd) {
+    // the backward knows every sample's Y, so while the soft cap is on the
+    // samples above it go straight to the full-queue pass (as the forward's
+    // would have left at it) instead of holding one main-pool block each
+    A.qcap = A.soft_cap;
     A.y_in = bwd->y_in;
     A.acc_live = bwd->live;
     A.acc_node = bwd->node;
