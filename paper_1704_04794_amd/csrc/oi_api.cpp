@@ -162,6 +162,7 @@ struct RoundSlot {
   std::vector<Phase> seg_phase;
   std::vector<size_t> pair_seg;  // segment of each pair accumulator
   uint64_t total = 0, off = 0, nch = 0, ptotal = 0;
+  uint32_t soft_budget = 0;  // the launch's budget of departures at the soft cap
   bool write_y = false, chunk_sums = false, giant_inline = false, timed = false;
   RoundSlot() = default;
   RoundSlot(const RoundSlot&) = delete;
@@ -205,6 +206,8 @@ struct oi_graph {
   int small_direct = 0;             // 0: automatic, 1: always, 2: never (see oi_set_routing)
   int64_t qcap_override = 0;        // > 0: queue entries per main-pool block
   uint32_t qcap_eff = 0;            // the large kernel's soft cap (<= large_qcap; 0: large_qcap)
+  uint32_t soft_budget = 0;         // departures at the soft cap allowed per launch
+  bool soft_bwd = false;            // the backward may send samples above the soft cap to the full-queue pass
   int variant = 0;
   bool use_tiny = true;
   uint32_t chunk = 256;
@@ -397,16 +400,16 @@ oi_status ensure_giant_pool(oi_graph* g) {
 // The large kernel's soft cap for the next launches.  A launch lasts as
 // long as its largest sample.  When a launch saw only a few samples with
 // more than big_mark activations (the rare giant cascades of a huge sparse
-// graph: at most four per block of the full-queue pass), the next launches
-// let such samples leave the main pool once they pass big_mark, for the
-// full-queue pass, whose 1024-thread blocks finish them side by side,
-// instead of each keeping one 256-thread block running long after the rest
-// of the launch.  At most two per full-queue block leave per launch (the
-// kernel's budget), so a launch with more of them than expected costs at
-// most two waves of that pass; after a launch with many of them (a graph
-// where most samples are that large) the soft cap is lifted again.
-// Decided from the previous forward launch; results never depend on it.  A
-// cap set by oi_set_routing is kept as set.
+// graph: at most four per full-queue block), the next launches let such
+// samples leave the main pool once they pass big_mark, for the full-queue
+// pass, whose 1024-thread blocks finish them side by side, instead of each
+// keeping one 256-thread block running long after the rest of the launch.
+// The kernel lets at most soft_budget samples leave per launch (two per
+// full-queue block; later ones go on in the main pool), so a misjudged
+// launch costs at most two waves of that pass.  After a launch with more
+// of them (a graph where most samples are that large) the soft cap is
+// lifted.  Decided from the previous forward launch; results never depend
+// on it.  A cap set by oi_set_routing is kept as set.
 uint32_t big_mark(const oi_graph* g) { return std::min<uint32_t>(kBigMark, g->large_qcap / 8); }
 
 oi_status adapt_qcap(oi_graph* g, const unsigned long long* ctl) {
@@ -422,8 +425,13 @@ oi_status adapt_qcap(oi_graph* g, const unsigned long long* ctl) {
       OI_TRY(ensure_giant_pool(g));
       g->qcap_eff = mark;
     }
+    g->soft_budget = 2u * (uint32_t)g->giant_blocks;
+    // the backward routes by the forward's Y, with no budget: the few
+    // samples above the soft cap go straight to the full-queue pass
+    g->soft_bwd = true;
   } else {
     g->qcap_eff = 0;
+    g->soft_bwd = false;
   }
   return OI_OK;
 }
@@ -471,7 +479,7 @@ oi::SampleLaunch make_launch(const oi_graph* g, const oi::Segment* d_segs, const
   A.nbig = reinterpret_cast<unsigned int*>(ctl + 14);
   A.big_mark = big_mark(g);
   A.soft_cap = g->qcap_eff ? g->qcap_eff : g->large_qcap;
-  A.soft_budget = 2u * (uint32_t)(g->giant_blocks > 0 ? g->giant_blocks : kGiantBlocksMax);
+  A.soft_budget = g->soft_budget;
   A.nsoft = reinterpret_cast<unsigned int*>(ctl + 15);
   // list1's storage is free once the small kernel has run: it holds list3
   A.list3 = g->d_def.as<unsigned long long>();
@@ -530,8 +538,8 @@ oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t
   return OI_OK;
 }
 
-void add_timing(oi_graph* g, const unsigned long long* hctl, uint64_t total, float tiny_ms, float small_ms,
-                float large_ms) {
+void add_timing(oi_graph* g, const unsigned long long* hctl, uint32_t soft_budget, uint64_t total, float tiny_ms,
+                float small_ms, float large_ms) {
   g->tm.tiny_ms += tiny_ms;
   g->tm.small_ms += small_ms;
   g->tm.large_ms += large_ms;
@@ -548,7 +556,7 @@ void add_timing(oi_graph* g, const unsigned long long* hctl, uint64_t total, flo
   g->tm.handed_full += hctl[12] & 0xffffffffull;
   // every sample that passed the soft cap took a ticket; those within the
   // budget (two per full-queue block) left
-  g->tm.left_soft += std::min<uint64_t>(hctl[15] & 0xffffffffull, 2ull * (uint64_t)std::max(g->giant_blocks, 0));
+  g->tm.left_soft += std::min<uint64_t>(hctl[15] & 0xffffffffull, (uint64_t)soft_budget);
 }
 
 oi_status elapsed(hipEvent_t a, hipEvent_t b, float* ms) {
@@ -595,10 +603,11 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
                                    total, seed, y_dev, e_dev, ctl, g->d_sums.as<unsigned long long>());
   const bool is_bwd = bwd != nullptr;
   if (is_bwd) {
-    // the backward knows every sample's Y, so while the soft cap is on the
-    // samples above it go straight to the full-queue pass (as the forward's
-    // would have left at it) instead of holding one main-pool block each
-    A.qcap = A.soft_cap;
+    // the backward knows every sample's Y, so while the soft cap is on (and
+    // the last forward launch had few samples above it) those samples go
+    // straight to the full-queue pass instead of holding one main-pool
+    // block each
+    if (g->soft_bwd) A.qcap = A.soft_cap;
     A.y_in = bwd->y_in;
     A.acc_live = bwd->live;
     A.acc_node = bwd->node;
@@ -634,7 +643,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     OI_TRY(elapsed(g->ev[0], g->ev[1], &t0));
     OI_TRY(elapsed(g->ev[1], g->ev[2], &t1));
     OI_TRY(elapsed(g->ev[2], g->ev[3], &t2));
-    add_timing(g, hctl, total, t0, t1, t2 + giant_ms);
+    add_timing(g, hctl, A.soft_budget, total, t0, t1, t2 + giant_ms);
   }
   return OI_OK;
 }
@@ -849,6 +858,7 @@ oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
   uint32_t* ydev = g->d_y.as<uint32_t>();
   oi::SampleLaunch A = make_launch(g, S.d_segs.as<oi::Segment>(), S.d_qs.as<oi::QueryDev>(), (int32_t)ns, total,
                                    seed, S.write_y ? ydev : nullptr, nullptr, res, res + S.sums_at());
+  S.soft_budget = A.soft_budget;
   S.timed = g->timing;
   // every operation of the round, in stream order (the result block is
   // cleared by a kernel: no memset node may enter a captured graph)
@@ -934,7 +944,7 @@ oi_status wait_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
     OI_TRY(elapsed(S.ev[1], S.ev[2], &t1));
     OI_TRY(elapsed(S.ev[2], S.ev[3], &t2));
     if (S.giant_inline) OI_TRY(elapsed(S.ev[4], S.ev[5], &t3));
-    add_timing(g, res, S.total, t0, t1, t2 + t3);
+    add_timing(g, res, S.soft_budget, S.total, t0, t1, t2 + t3);
   }
   return OI_OK;
 }
