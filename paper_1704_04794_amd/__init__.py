@@ -113,12 +113,18 @@ class Graph:
         return oi_autotune(self.h, off, seeds, q, pilot, run_seed)
 
     def timing(self, enable=None):
+        """Kernel timing with HIP events: timing(True) turns it on and resets
+        the counters, timing(False) turns it off; returns the counters."""
         if enable is not None:
             oi_timing_enable(self.h, enable)
         return oi_timing_get(self.h)
 
     def tune(self, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1, small_direct=-1, large_qcap=-1,
              pipeline=None):
+        """Sampler knobs (oi_set_tuning, oi_set_routing, oi_set_pipeline); -1
+        (or None) keeps a setting.  large_qcap > 0 fixes the large kernel's
+        queue size, 0 restores the default adaptive soft cap.  Results never
+        depend on any of them."""
         oi_set_tuning(self.h, variant, chunk, tiny, tiny_chunk, round_max)
         if small_direct >= 0 or large_qcap >= 0:
             oi_set_routing(self.h, small_direct, large_qcap)
