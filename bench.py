@@ -14,6 +14,13 @@ library's stream) and the CPU oracle's rate on a bounded sample of the same
 query.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+    python bench.py --workload cl4m [--queries Q] [--eps E] [--no-autotune]
+        seed-set estimates/s, batched vs one at a time, on the 4M-node
+        weighted-cascade graph, with the large-cascade kernel's roofline
+    python bench.py --workload cl100m
+        the 1e8-node / 1.5e9-edge graph: fixed-count throughput for
+        |S| = 1, 10, 100, a SIEA estimate, the queue-cap comparison and the
+        backward over all edges
 """
 from __future__ import annotations
 
