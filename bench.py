@@ -255,7 +255,7 @@ def batched_vs_single(P, args):
     g, sets, extra = make_config("cl4m")
     log(f"cl4m graph n={g.n} m={g.m} built in {time.perf_counter() - t:.1f}s")
     half = len(sets) // 2
-    k = max(1, args.queries // 2)
+    k = max(1, (args.queries or 32) // 2)
     rng = np.random.default_rng(7)
     pick = np.concatenate([rng.choice(half, size=k, replace=False),
                            half + rng.choice(len(sets) - half, size=k, replace=False)])
@@ -307,6 +307,46 @@ def batched_vs_single(P, args):
             "batched_samples_per_s": samples / tb, "large_kernel": large, "autotune": tune}
 
 
+def batched_vs_single_small(P, args):
+    """Seed-set estimates/s, batched vs one at a time, where one query alone
+    leaves the GPU idle: the 2k-node ER weighted-cascade graph, Q seeded
+    single-node seed sets, SOIEA at eps = 0.05, delta = 1e-3.  Each estimate
+    needs only a few million short samples, so one at a time it is bound by
+    the per-round launch and read-back; batched, every round serves all
+    unfinished queries."""
+    import numpy as np
+    import torch
+
+    from oi_inputs import make_config, uniform_seed_set
+    g, _, _ = make_config("er2k")
+    q = args.queries or 256
+    sub = [uniform_seed_set(g, 1, 1000 + i) for i in range(q)]
+    qids = np.arange(q, dtype=np.uint32)
+    eps = args.eps if args.eps > 0 else 0.05
+    delta = 1e-3
+    G = P.Graph.from_inputs(g)
+    G.estimate(sub[0], 0.5, delta, query_id=0)  # warm up kernels and workspaces
+    G.estimate_batch(sub[:4], 0.5, delta, query_ids=qids[:4])
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    batch = G.estimate_batch(sub, eps, delta, query_ids=qids)
+    tb = time.perf_counter() - t
+    log(f"batched: {q} sets in {tb:.3f}s")
+    t = time.perf_counter()
+    single = [G.estimate(S, eps, delta, query_id=int(i)) for S, i in zip(sub, qids)]
+    ts = time.perf_counter() - t
+    log(f"one at a time: {q} sets in {ts:.3f}s")
+    same = all(a["oi"] == b["oi"] and a["T"] == b["T"] for a, b in zip(batch, single))
+    samples = sum(r["samples_x"] + r["samples_xp"] for r in batch)
+    G.close()
+    return {"metric": "seed-set estimates/s, batched vs one at a time", "workload":
+            f"er2k: Erdos-Renyi n=2000 m=20000 WC p, {q} seeded single-node seed sets, SOIEA eps={eps} "
+            f"delta={delta}",
+            "batched_estimates_per_s": q / tb, "single_estimates_per_s": q / ts, "speedup": ts / tb,
+            "identical_results": same, "samples": samples, "batched_samples_per_s": samples / tb,
+            "rounds_per_estimate": sum(r["rounds"] for r in single) / q}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -318,10 +358,12 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--pipeline", type=int, choices=(0, 1, 2), default=None,
                     help="RSA rounds: 0 read back one at a time, 1 queued (default), 2 queued, one graph each")
-    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m"), default="cl1m",
+    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m", "er2k"), default="cl1m",
                     help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time; "
-                         "cl100m: the billion-edge graph")
-    ap.add_argument("--queries", type=int, default=32, help="cl4m: number of seed sets in the subset")
+                         "cl100m: the billion-edge graph; er2k: batched vs one-at-a-time where one query "
+                         "leaves the GPU idle")
+    ap.add_argument("--queries", type=int, default=None,
+                    help="cl4m: seed sets in the subset (default 32); er2k: seed sets (default 256)")
     ap.add_argument("--no-autotune", action="store_true", help="cl4m: keep the default sampler schedule")
     ap.add_argument("--eps", type=float, default=-1.0, help="cl4m: eps (default: the workload's 0.1)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -351,6 +393,9 @@ def main():
         log("copied 1 GiB device-to-device for counter calibration")
     if args.workload == "cl4m":
         print(json.dumps(batched_vs_single(P, args)), flush=True)
+        return
+    if args.workload == "er2k":
+        print(json.dumps(batched_vs_single_small(P, args)), flush=True)
         return
     if args.workload == "cl100m":
         print(json.dumps(billion_edge(P, args)), flush=True)
