@@ -558,14 +558,17 @@ int oo_rsa(oo_next_fn next, void *ctx, double eps, double delta, double a, doubl
 }
 
 /* Stream source backed by two caller arrays (for tests of the stopping rules). */
+/* Array streams for tests.  Past its end a stream is marked overrun (the
+ * call then reports OO_ERANGE) and yields UINT32_MAX, so that every
+ * stopping loop still ends: a stream of zeros would never reach a threshold. */
 typedef struct { const uint32_t *x; uint64_t nx; const uint32_t *xp; uint64_t nxp; int overrun; } arr_ctx;
 static uint32_t arr_next(void *c, uint32_t stream, uint64_t i)
 {
     arr_ctx *a = c;
-    if (stream == 0) { if (i < a->nx) return a->x[i]; a->overrun = 1; return 0; }
+    if (stream == 0) { if (i < a->nx) return a->x[i]; a->overrun = 1; return UINT32_MAX; }
     if (i < a->nxp) return a->xp[i];
     a->overrun = 1;
-    return 0;
+    return UINT32_MAX;
 }
 
 int oo_rsa_arrays(const uint32_t *x, uint64_t nx, const uint32_t *xp, uint64_t nxp,

@@ -5,9 +5,11 @@ The threshold formulas themselves have no printed worked values; they are
 pinned here only through their consequences: closed forms of the stopping
 index on constant streams (which pin the control flow: which stream, which
 index, which estimate feeds which step), the overshoot bound of the proof of
-Theorem 3 (Upsilon <= sum X <= Upsilon + b), and the (eps, delta) guarantee
-of Theorems 3/4 measured as a failure frequency.  In that sense the
-threshold arithmetic is only partially pinned.
+Theorem 3 (Upsilon <= sum X <= Upsilon + b), the (eps, delta) guarantee of
+Theorems 3/4 measured as a failure frequency, and both claims of Theorem 3
+computed exactly for Bernoulli streams down to delta = 1e-8 (which bound
+the GSRA threshold from below to within 25%).  In that sense the threshold
+arithmetic is only partially pinned.
 """
 import math
 
@@ -139,3 +141,47 @@ def test_estimate_degenerate_and_invalid():
         O.estimate(g, [16], 0.1, 0.1, 0, 0, SEED)
     with pytest.raises(O.OracleError):
         O.estimate(g, [], 0.1, 0.1, 0, 0, SEED)
+
+
+def _gsra_bernoulli_failures(r, ups, eps, p):
+    """For X_i ~ Bernoulli(p) on [a, b] = [0, 1] the sum grows by one per
+    success, so a stop at the r-th success makes T negative binomial:
+    Pr[T <= t] = Pr[Binomial(t, p) >= r].  Returns the exact probabilities
+    of the two events Theorem 3 bounds: |r/T - p| > eps p, and
+    T > (1 + eps) Upsilon / p."""
+    from scipy.stats import binom
+    t_lo = math.floor(r / ((1.0 - eps) * p))            # r/T < (1 - eps) p  <=>  T > t_lo
+    low = binom.cdf(r - 1, t_lo, p)
+    t_hi = math.ceil(r / ((1.0 + eps) * p)) - 1         # r/T > (1 + eps) p  <=>  T <= t_hi
+    high = binom.sf(r - 1, t_hi, p) if t_hi >= r else 0.0
+    t_cap = math.floor((1.0 + eps) * ups / p)
+    return low + high, binom.cdf(r - 1, t_cap, p)
+
+
+@pytest.mark.parametrize("eps", [0.05, 0.25, 0.9])
+@pytest.mark.parametrize("delta", [0.1, 1e-4, 1e-8])
+def test_gsra_theorem3_exact_on_bernoulli_streams(eps, delta):
+    """Theorem 3 computed exactly, with no sampling: with the oracle's
+    threshold, for Bernoulli streams of every mean p from 1e-4 to 1,
+    Pr[|mu_hat - p| > eps p] < delta and Pr[T > (1 + eps) Upsilon / p] <
+    delta / 2.  The stopping index r comes from the oracle's own loop (an
+    all-ones stream stops at r = ceil(Upsilon)), and a random 0/1 stream is
+    checked to stop exactly at its r-th success.  The theorem bounds the
+    threshold from below only; at delta = 1e-8 a threshold 25% smaller
+    breaks the first claim, which pins the threshold to within that."""
+    ones = np.ones(2_000_000, np.uint32)
+    g = O.gsra_array(ones, eps, delta, 0.0, 1.0)
+    r, ups = g["T"], g["ups"]
+    assert r == math.ceil(ups) and g["h"] == r
+    x = (np.random.default_rng(5).random(40 * r + 1000) < 0.05).astype(np.uint32)
+    s = O.gsra_array(x, eps, delta, 0.0, 1.0)
+    assert s["h"] == r and s["T"] == int(np.flatnonzero(x)[r - 1]) + 1 and s["mu"] == r / s["T"]
+    worst_acc = worst_len = 0.0
+    for p in np.geomspace(1e-4, 1.0, 25):
+        acc, length = _gsra_bernoulli_failures(r, ups, eps, p)
+        worst_acc, worst_len = max(worst_acc, acc), max(worst_len, length)
+    assert worst_acc < delta and worst_len < delta / 2, (worst_acc / delta, worst_len / (delta / 2))
+    if delta == 1e-8:
+        r_small = math.ceil(0.75 * ups)
+        bad = max(_gsra_bernoulli_failures(r_small, 0.75 * ups, eps, p)[0] for p in np.geomspace(1e-4, 1.0, 25))
+        assert bad > delta
