@@ -185,3 +185,17 @@ def test_gsra_theorem3_exact_on_bernoulli_streams(eps, delta):
         r_small = math.ceil(0.75 * ups)
         bad = max(_gsra_bernoulli_failures(r_small, 0.75 * ups, eps, p)[0] for p in np.geomspace(1e-4, 1.0, 25))
         assert bad > delta
+
+
+@pytest.mark.timeout(60)
+def test_short_array_streams_are_reported_not_spun():
+    """A stream shorter than the stopping index ends the run with an error
+    (it used to leave the stopping loop waiting for a sum that zeros past
+    the end of the array could never reach)."""
+    with pytest.raises(O.OracleError):
+        O.gsra_array(np.ones(4, np.uint32), 0.5, 0.1, 0.0, 1.0)
+    with pytest.raises(O.OracleError):
+        O.rsa_arrays(np.ones(4, np.uint32), np.ones(4, np.uint32), 0.1, 0.1, 1.0, 2.0)
+    x = np.ones(1_000_000, np.uint32)
+    with pytest.raises(O.OracleError):  # step 1 fits, the pairs of step 2 do not
+        O.rsa_arrays(x, np.ones(2, np.uint32), 0.1, 0.1, 1.0, 2.0)
