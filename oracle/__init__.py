@@ -58,11 +58,12 @@ def lib():
         L.oo_selection.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp]
         L.oo_rsa_arrays.argtypes = [vp, u64, vp, u64, dbl, dbl, dbl, dbl, dbl, dbl, _P(RsaResult)]
         L.oo_gsra_array.argtypes = [vp, u64, dbl, dbl, dbl, dbl, dbl, dbl, _P(dbl), _P(u64), _P(u64), _P(dbl)]
+        L.oo_rsa_plan.argtypes = [dbl, dbl, dbl, dbl, dbl, dbl, u64, vp, vp, vp, vp, vp, vp, vp]
         L.oo_estimate.argtypes = g + [vp, i64, dbl, dbl, C.c_int, u32, u32, _P(dbl), _P(dbl), _P(dbl),
                                       _P(i64), _P(RsaResult)]
         L.oo_exact.argtypes = g + [vp, i64, _P(dbl), vp, vp]
         L.oo_backward.argtypes = g + [vp, i64, u32, u32, u64, u64, vp, vp, _P(u64), _P(dbl), C.c_int]
-        for f in ("oo_sample_fixed", "oo_stage1", "oo_selection", "oo_rsa_arrays", "oo_gsra_array",
+        for f in ("oo_sample_fixed", "oo_stage1", "oo_selection", "oo_rsa_arrays", "oo_gsra_array", "oo_rsa_plan",
                   "oo_estimate", "oo_exact", "oo_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -183,6 +184,37 @@ def gsra_array(x, eps, delta, a, b, scale=1.0, offset=0.0):
                              C.byref(T), C.byref(h), C.byref(ups))
     _chk("gsra_array", rc)
     return dict(mu=mu.value, T=T.value, h=h.value, ups=ups.value)
+
+
+def rsa_plan(eps, delta, a, b, h1, T1, D=None, scale=1.0, offset=0.0):
+    """RSA's step-2 and step-3 sizes (Alg. 3, eps < 1/4) as the oracle's
+    controller computes them from the sums it observes: step 1 stopped after
+    T1 samples whose Y sum to h1; D (optional) is step 2's integer sum of
+    squared paired differences of Y' (below 2^128).  Arrays of equal length.
+    Returns dict(nsigma, T (None without D), ups1 (step 1's threshold), ups,
+    ups2)."""
+    h1 = np.ascontiguousarray(np.atleast_1d(h1), dtype=np.uint64)
+    T1 = np.ascontiguousarray(np.atleast_1d(T1), dtype=np.uint64)
+    n = h1.size
+    assert T1.size == n
+    ns = np.zeros(n, np.uint64)
+    T = None
+    dlo = dhi = None
+    if D is not None:
+        Da = np.atleast_1d(D)
+        if Da.dtype == object:  # Python integers, possibly of 65..128 bits
+            dlo = np.array([int(d) & ((1 << 64) - 1) for d in Da], dtype=np.uint64)
+            dhi = np.array([int(d) >> 64 for d in Da], dtype=np.uint64)
+        else:
+            dlo = np.ascontiguousarray(Da, dtype=np.uint64)
+            dhi = np.zeros(n, np.uint64)
+        assert dlo.size == n
+        T = np.zeros(n, np.uint64)
+    thr = np.zeros(3, np.float64)
+    rc = lib().oo_rsa_plan(float(eps), float(delta), float(a), float(b), float(scale), float(offset), n,
+                           _ptr(h1), _ptr(T1), _ptr(dlo), _ptr(dhi), _ptr(ns), _ptr(T), _ptr(thr))
+    _chk("rsa_plan", rc)
+    return dict(nsigma=ns, T=T, ups1=float(thr[0]), ups=float(thr[1]), ups2=float(thr[2]))
 
 
 def estimate(g, seeds, eps, delta, mode: int, qid: int, seed: int):

@@ -509,6 +509,39 @@ static void gsra(oo_next_fn next, void *ctx, double eps, double delta, double a,
     *T_out = T; *h_out = h; *ups_out = ups; *early = 0;
 }
 
+/* Alg. 3, step 2: the number of pairs of X' from step 1's estimate mu' (R10). */
+static int rsa_nsigma(double eps, double delta, double a, double b, double mu1,
+                      double *ups_out, double *ups2_out, uint64_t *nsigma)
+{
+    double se = sqrt(eps);
+    double L = log(2.0 / delta);
+    double ups = upsilon(eps, delta, a, b);
+    double ups2 = 2.0 * (1.0 + se) / (1.0 - se) * (1.0 + log(1.5) / L) * ups;
+    double ns = ceil(ups2 * eps / mu1);
+    if (!(ns < 4.0e18)) return OO_ERANGE;
+    *nsigma = ns < 1.0 ? 1 : (uint64_t)ns;
+    if (ups_out) *ups_out = ups;
+    *ups2_out = ups2;
+    return OO_OK;
+}
+
+/* Alg. 3, step 3: the number of samples T from mu', the 128-bit sum D of
+ * squared paired differences of the integer stream Y', N_sigma and Upsilon_2
+ * (R10, R11: the differences of X' = scale * Y' + offset are scale times
+ * those of Y'). */
+static int rsa_steps3(double eps, double a, double b, double scale, double mu1, double ups2,
+                      uint64_t nsigma, oo_u128 D, uint64_t *T)
+{
+    double Delta = scale * scale * (double)D / 2.0;
+    double rho1 = Delta / (double)nsigma;
+    double rho2 = eps * mu1 * (b - a);
+    double rho = rho1 > rho2 ? rho1 : rho2;
+    double tt = ceil(ups2 * rho / (mu1 * mu1 * (b - a)));
+    if (!(tt < 4.0e18)) return OO_ERANGE;
+    *T = tt < 1.0 ? 1 : (uint64_t)tt;
+    return OO_OK;
+}
+
 /* Alg. 3 (RSA) with readings R10, R11. */
 int oo_rsa(oo_next_fn next, void *ctx, double eps, double delta, double a, double b,
            double scale, double offset, oo_rsa_result *r)
@@ -526,12 +559,8 @@ int oo_rsa(oo_next_fn next, void *ctx, double eps, double delta, double a, doubl
     /* step 1 */
     gsra(next, ctx, se, delta / 3.0, a, b, scale, offset, &r->mu1, &r->T1, &r->h1, &r->ups1, &r->early);
     /* step 2 */
-    double L = log(2.0 / delta);
-    r->ups = upsilon(eps, delta, a, b);
-    r->ups2 = 2.0 * (1.0 + se) / (1.0 - se) * (1.0 + log(1.5) / L) * r->ups;
-    double ns = ceil(r->ups2 * eps / r->mu1);
-    if (!(ns < 4.0e18)) return OO_ERANGE;
-    r->nsigma = ns < 1.0 ? 1 : (uint64_t)ns;
+    int rc = rsa_nsigma(eps, delta, a, b, r->mu1, &r->ups, &r->ups2, &r->nsigma);
+    if (rc) return rc;
     oo_u128 D = 0;
     for (uint64_t i = 0; i < r->nsigma; ++i) {
         uint32_t y0 = next(ctx, 1, 2 * i), y1 = next(ctx, 1, 2 * i + 1);
@@ -540,20 +569,52 @@ int oo_rsa(oo_next_fn next, void *ctx, double eps, double delta, double a, doubl
     }
     r->D_lo = (uint64_t)D;
     r->D_hi = (uint64_t)(D >> 64);
-    double Delta = scale * scale * (double)D / 2.0;
-    double rho1 = Delta / (double)r->nsigma;
-    double rho2 = eps * r->mu1 * (b - a);
-    double rho = rho1 > rho2 ? rho1 : rho2;
     /* step 3 */
-    double tt = ceil(r->ups2 * rho / (r->mu1 * r->mu1 * (b - a)));
-    if (!(tt < 4.0e18)) return OO_ERANGE;
-    r->T = tt < 1.0 ? 1 : (uint64_t)tt;
+    rc = rsa_steps3(eps, a, b, scale, r->mu1, r->ups2, r->nsigma, D, &r->T);
+    if (rc) return rc;
     uint64_t h = 0;
     for (uint64_t i = 0; i < r->T; ++i) h += next(ctx, 0, i);
     r->hT = h;
     r->mu = sumx(scale, offset, h, r->T) / (double)r->T;
     r->drawn_x = r->T > r->T1 ? r->T : r->T1;
     r->drawn_xp = 2 * r->nsigma;
+    return OO_OK;
+}
+
+/*
+ * The decisions of RSA (Alg. 3, eps < 1/4) as functions of the integer sums
+ * it observes, through the same code as oo_rsa: for each of the `count`
+ * cases, step 1 ended after T1[i] samples whose Y summed to h1[i] (mu' =
+ * (scale * h1 + offset * T1) / T1, R11), giving nsigma_out[i]; if D_lo is not
+ * NULL, step 2's sum of squared paired differences of Y' was D_hi[i] * 2^64 +
+ * D_lo[i], giving T_out[i].  thr_out (may be NULL) receives the step-1 GSRA
+ * threshold, Upsilon(eps, delta) and Upsilon_2.  For tests that evaluate
+ * Theorem 4 exactly.
+ */
+int oo_rsa_plan(double eps, double delta, double a, double b, double scale, double offset,
+                uint64_t count, const uint64_t *h1, const uint64_t *T1, const uint64_t *D_lo,
+                const uint64_t *D_hi, uint64_t *nsigma_out, uint64_t *T_out, double *thr_out)
+{
+    if (!(eps > 0.0 && eps < 0.25) || !(delta > 0.0 && delta < 0.5) || !(b > a) || !(a >= 0.0))
+        return OO_EINVAL;
+    double se = sqrt(eps);
+    if (thr_out) {
+        thr_out[0] = upsilon(se, delta / 3.0, a, b);
+        thr_out[1] = upsilon(eps, delta, a, b);
+    }
+    for (uint64_t i = 0; i < count; ++i) {
+        if (T1[i] == 0) return OO_EINVAL;
+        double mu1 = sumx(scale, offset, h1[i], T1[i]) / (double)T1[i];
+        double ups, ups2;
+        int rc = rsa_nsigma(eps, delta, a, b, mu1, &ups, &ups2, &nsigma_out[i]);
+        if (rc) return rc;
+        if (thr_out) thr_out[2] = ups2;
+        if (D_lo) {
+            oo_u128 D = ((oo_u128)D_hi[i] << 64) | (oo_u128)D_lo[i];
+            rc = rsa_steps3(eps, a, b, scale, mu1, ups2, nsigma_out[i], D, &T_out[i]);
+            if (rc) return rc;
+        }
+    }
     return OO_OK;
 }
 

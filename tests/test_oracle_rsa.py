@@ -1,15 +1,13 @@
 """Pins of the oracle's stopping rules (GSRA, Alg. 2; RSA, Alg. 3) and of
-SOIEA / SIEA (Algs. 4, 5).
-
-The threshold formulas themselves have no printed worked values; they are
-pinned here only through their consequences: closed forms of the stopping
-index on constant streams (which pin the control flow: which stream, which
-index, which estimate feeds which step), the overshoot bound of the proof of
-Theorem 3 (Upsilon <= sum X <= Upsilon + b), the (eps, delta) guarantee of
-Theorems 3/4 measured as a failure frequency, and both claims of Theorem 3
-computed exactly for Bernoulli streams down to delta = 1e-8 (which bound
-the GSRA threshold from below to within 25%).  In that sense the threshold
-arithmetic is only partially pinned.
+SOIEA / SIEA (Algs. 4, 5), by their consequences: closed forms of the
+stopping index on constant streams (which pin the control flow: which
+stream, which index, which estimate feeds which step), the overshoot bound
+of the proof of Theorem 3 (Upsilon <= sum X <= Upsilon + b), the (eps,
+delta) guarantee of Theorems 3/4 measured as a failure frequency, and both
+claims of Theorem 3 computed exactly for Bernoulli streams down to
+delta = 1e-8 (which bound the GSRA threshold from below to within 25%).
+Theorem 4 computed exactly, and the printed expressions of every RSA
+quantity, are in test_oracle_rsa_exact.py.
 """
 import math
 
