@@ -122,8 +122,11 @@ oi_status oi_stage1_table(oi_graph* g, const int32_t* seeds, int64_t k, int64_t 
  * stream `stream` (0 = X, 1 = X') of the query (query_id, seeds).
  * y_out: device uint32[count] (or NULL) receives Y per sample;
  * e_out: device uint64[count] (or NULL) receives the examined-edge count per
- * sample.  sums (host, may be NULL): sum_y, edges_examined, beta0, k, l.
- * If beta_0 = 0 nothing is sampled and y_out is left untouched.
+ * sample.  sums (host, may be NULL): sum_y, edges_examined, beta0, k, l, and
+ * the fixed-count estimate of Lemma 2 over these samples: mu = mean(Y),
+ * oi = beta_0 * mu, is = oi + |S| (T = count, hT = sum_y).
+ * If beta_0 = 0 nothing is sampled, y_out is left untouched and oi = 0,
+ * is = |S|.
  */
 oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
                           uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out,

@@ -144,7 +144,8 @@ def sample_fixed(g, seeds, qid: int, seed: int, stream: int, first: int, count: 
                  want_y: bool = True, want_e: bool = False, nthreads: int | None = None):
     """Per-sample Y (uint32) and E (uint64) of samples first..first+count-1.
 
-    Returns dict(y, e, sum_y, sum_e, beta0)."""
+    Returns dict(y, e, sum_y, sum_e, beta0, oi, is_) with the fixed-count
+    estimate oi = beta_0 * mean(Y) (Lemma 2) and is_ = oi + |S|."""
     gg = _graph(g)
     s = _seeds(seeds)
     y = np.zeros(count, np.uint32) if want_y else None
@@ -155,7 +156,12 @@ def sample_fixed(g, seeds, qid: int, seed: int, stream: int, first: int, count: 
     rc = lib().oo_sample_fixed(*_gargs(gg), _ptr(s), s.size, qid, seed, stream, first, count,
                                _ptr(y), _ptr(e), _ptr(sums), _ptr(b0), nt)
     _chk("sample_fixed", rc)
-    return dict(y=y, e=e, sum_y=int(sums[0]), sum_e=int(sums[1]), beta0=float(b0[0]))
+    # the fixed-count estimate of Lemma 2 (and the FPRAS of Sec. 3.2):
+    # OI = beta_0 * mean(Y); IS = OI + |S| (Eq. def)
+    k = int(np.unique(s).size)
+    b = float(b0[0])
+    oi = b * (int(sums[0]) / count) if (b > 0.0 and count > 0) else 0.0
+    return dict(y=y, e=e, sum_y=int(sums[0]), sum_e=int(sums[1]), beta0=b, oi=oi, is_=oi + k)
 
 
 def selection(g, seeds, qid: int, seed: int, stream: int, first: int, count: int):

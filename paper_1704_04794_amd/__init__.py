@@ -40,6 +40,9 @@ class Graph:
         self.n = int(n)
         self.m = int(col.shape[0])
         self.h = oi_graph_create(self.n, self.m, row_ptr, col, p, 1 if dev else 0, stream)
+        # bumped by every change of the edge probabilities (set_probs,
+        # set_theta), so that holders of earlier results can tell
+        self.version = 0
 
     @classmethod
     def from_inputs(cls, g, stream=None):
@@ -59,12 +62,14 @@ class Graph:
 
     def set_probs(self, p):
         dev = _is_device_tensor(p)
+        self.version += 1
         oi_graph_set_probs(self.h, p.contiguous() if dev else np.ascontiguousarray(p, np.float32),
                            1 if dev else 0)
 
     def set_theta(self, theta):
         """p = sigmoid(theta), computed by the library on the GPU."""
         dev = _is_device_tensor(theta)
+        self.version += 1
         oi_graph_set_theta(self.h, theta.contiguous() if dev else np.ascontiguousarray(theta, np.float32),
                            1 if dev else 0)
 

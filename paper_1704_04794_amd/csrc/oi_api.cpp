@@ -1417,6 +1417,12 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
     else
       r.samples_xp = count;
   }
+  // the fixed-count estimate of Lemma 2: OI = beta_0 * mean(Y), IS = OI + |S|
+  r.T = count;
+  r.hT = r.sum_y;
+  r.mu = count ? (double)r.sum_y / (double)count : 0.0;
+  r.oi = Q.beta0 > 0.0 && count ? Q.beta0 * r.mu : 0.0;
+  r.is = r.oi + (double)Q.S.size();
   if (sums) *sums = r;
   return OI_OK;
 }

@@ -156,6 +156,34 @@ def test_autograd_function(P):
     (2.0 * oi).backward()
     gt = _gpu_grad(P, G, S, 100_000, param=P.OI_PARAM_THETA)
     np.testing.assert_allclose(th.grad.cpu().numpy(), 2.0 * gt, rtol=1e-6, atol=1e-9)
+    # the forward's value is the library's fixed-count estimate (Lemma 2)
     y, _, r = G.sample_fixed(S, 100_000)
-    assert abs(oi.item() - r["beta0"] * r["sum_y"] / 100_000) < 1e-12
+    assert oi.item() == r["oi"]
+    assert r["oi"] == r["beta0"] * (r["sum_y"] / 100_000)
+    assert r["is_"] == r["oi"] + 2
+    G.close()
+
+
+def test_autograd_two_forwards_on_one_graph(P):
+    """loss = f(theta_1) + f(theta_2) through one Graph: each backward runs
+    with the probabilities of its own forward (the second forward changed
+    the graph's p before either backward ran)."""
+    import torch
+    from paper_1704_04794_amd.autograd import outward_influence
+    g = tiny16_graph()
+    theta, _ = sigmoid_theta_probs(g, 40)
+    G = P.Graph.from_inputs(g)
+    S = [1, 4]
+    N = 50_000
+    th1 = torch.from_numpy(theta).cuda().requires_grad_(True)
+    th2 = torch.from_numpy(theta + 0.7).cuda().requires_grad_(True)
+    loss = outward_influence(th1, G, S, N) + 3.0 * outward_influence(th2, G, S, N)
+    loss.backward()
+    G.set_theta(th1.detach())
+    ref1 = _gpu_grad(P, G, S, N, param=P.OI_PARAM_THETA)
+    G.set_theta(th2.detach())
+    ref2 = _gpu_grad(P, G, S, N, param=P.OI_PARAM_THETA)
+    assert np.abs(ref1 - ref2).max() > 1e-3  # the two points differ
+    np.testing.assert_allclose(th1.grad.cpu().numpy(), ref1, rtol=1e-6, atol=1e-9)
+    np.testing.assert_allclose(th2.grad.cpu().numpy(), 3.0 * ref2, rtol=1e-6, atol=1e-9)
     G.close()

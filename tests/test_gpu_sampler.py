@@ -92,7 +92,8 @@ def test_er2k_workload_bit_exact(P):
     """The ER n=2000 m=20000 weighted-cascade workload: 100,000 samples, query 0."""
     g, sets, extra = make_config("er2k")
     r = _compare(P, g, sets[0], extra["samples"], label="er2k")
-    assert r["beta0"] * r["sum_y"] / extra["samples"] > 0.0
+    o = O.sample_fixed(g, sets[0], 0, RUN_SEED, 0, 0, extra["samples"], want_y=False)
+    assert r["oi"] == o["oi"] > 0.0 and r["is_"] == o["is_"] == r["oi"] + 1
 
 
 @pytest.mark.parametrize("variant,tiny", [(0, 1), (1, 1), (2, 1), (3, 1), (4, 1), (5, 1), (0, 0), (1, 0)])
