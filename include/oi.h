@@ -133,6 +133,26 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
                           oi_result* sums);
 
 /*
+ * oi_sample_fixed for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * the same samples, outputs and sums as oi_sample_fixed, with no hipMalloc,
+ * hipFree or other allocating library call.  Its working memory (Stage-1
+ * table, launch control block, hand-over lists, the large-cascade kernel's
+ * bitmaps and queues) is one static device array of 64 MiB, which every GPU
+ * the library runs on holds until the process ends.  y_out (device
+ * uint32[count]) is required; e_out (device uint64[count]) may be NULL.
+ * Limits: n <= 2^22 nodes, a Stage-1 table of at most 2^18 entries, at most
+ * 2^16 distinct seeds, else OI_ERANGE; the graph's device must be current,
+ * else OI_EINVAL.  Samples are drawn in launches of up to 2^19.  The array is
+ * shared by every call on a GPU and keeps the last call's contents (the call
+ * clears what must start empty): calls that overlap on one GPU, from any
+ * graph or thread, race and must not be made.
+ */
+oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
+                                  uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out,
+                                  uint64_t* e_out, oi_result* sums);
+
+/*
  * (eps, delta)-estimate of OI(S) and IS(S) = OI(S) + |S| (Sec. 2, estimation
  * problems) by SOIEA (Alg. 4) or SIEA (Alg. 5) with RSA (Alg. 3).
  * Requires 0 < eps < 1 and 0 < delta < 1/2.  beta_0 = 0 gives OI = 0,

@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -508,7 +509,8 @@ oi::SampleLaunch make_giant_launch(const oi_graph* g, const oi::SampleLaunch& A,
 
 // tiny -> small -> large kernels of one launch over A.total samples on
 // stream st; ev (four events, or null) brackets the three.
-oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t* ev, hipStream_t st) {
+oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t* ev, hipStream_t st,
+                       int large_blocks) {
   const uint64_t want_waves = (A.total + 63) / 64;
   int bpc = 0;
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
@@ -533,7 +535,7 @@ oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t
     HIP_TRY(oi::launch_small(g->variant, is_bwd, A, blocks, st));
   }
   if (ev) HIP_TRY(hipEventRecord(ev[2], st));
-  HIP_TRY(oi::launch_large(is_bwd, A, g->large_blocks, st));
+  HIP_TRY(oi::launch_large(is_bwd, A, large_blocks, st));
   if (ev) HIP_TRY(hipEventRecord(ev[3], st));
   return OI_OK;
 }
@@ -614,7 +616,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
     A.acc_tab = bwd->tab;
     A.sbits = bwd->sbits;
   }
-  OI_TRY(launch_tiers(g, A, is_bwd, g->timing ? g->ev : nullptr, g->stream));
+  OI_TRY(launch_tiers(g, A, is_bwd, g->timing ? g->ev : nullptr, g->stream, g->large_blocks));
   unsigned long long hctl[16] = {0};
   HIP_TRY(hipMemcpyAsync(hctl, g->d_ctl.p, sizeof(hctl), hipMemcpyDeviceToHost, g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
@@ -868,7 +870,7 @@ oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
     if (!S.pair_seg.empty())
       HIP_TRY(hipMemcpyAsync(S.d_pairs.p, pd, S.pair_seg.size() * sizeof(PairDesc), hipMemcpyHostToDevice, st));
     HIP_TRY(oi::launch_clear_u64(res, S.chunks_at(), st));
-    OI_TRY(launch_tiers(g, A, false, S.timed ? S.ev : nullptr, st));
+    OI_TRY(launch_tiers(g, A, false, S.timed ? S.ev : nullptr, st, g->large_blocks));
     if (S.giant_inline) {
       const oi::SampleLaunch B = make_giant_launch(g, A, res);
       if (S.timed) HIP_TRY(hipEventRecord(S.ev[4], st));
@@ -1203,6 +1205,61 @@ oi_status validate_probs(const std::vector<float>& p) {
   return OI_OK;
 }
 
+// ---------------------------------------------------------------------------
+// fixed-count sampling without allocation (oi_sample_fixed_noalloc)
+// ---------------------------------------------------------------------------
+constexpr size_t kNaBytes = 64ull << 20;     // the scratch array
+constexpr int64_t kNaMaxN = 1ll << 22;       // nodes
+constexpr int64_t kNaMaxL = 1ll << 18;       // Stage-1 entries
+constexpr int64_t kNaMaxK = 1ll << 16;       // seeds after removing duplicates
+constexpr uint64_t kNaLaunch = 1ull << 19;   // samples per sampling launch
+constexpr int64_t kNaQcap = 1ll << 16;       // queue entries per main-pool block
+constexpr int kNaMaxDevices = 64;
+
+}  // namespace
+
+// Device memory of oi_sample_fixed_noalloc: Stage-1 table, launch control
+// block, hand-over lists and the large-cascade kernel's bitmaps and queues.
+// Every GPU the library runs on holds its own copy until the process ends.
+// In host code this name is not a device address: the address comes from
+// hipGetSymbolAddress, once per device (na_scratch).
+static __device__ __align__(256) unsigned char scratch[kNaBytes];
+
+namespace {
+
+std::mutex g_na_mu;
+void* g_na_ptr[kNaMaxDevices] = {};
+
+// The device address of `scratch` on the current device, looked up on the
+// first call made with that device current.
+oi_status na_scratch(int dev, char** out) {
+  if (dev < 0 || dev >= kNaMaxDevices) return fail(OI_ERANGE, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_na_mu);
+  if (!g_na_ptr[dev]) {
+    void* p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(OI_EHIP, "hipGetSymbolAddress returned no address for the scratch array");
+    g_na_ptr[dev] = p;
+  }
+  *out = static_cast<char*>(g_na_ptr[dev]);
+  return OI_OK;
+}
+
+// Consecutive 256-byte aligned pieces of the scratch array.
+struct Carve {
+  char* base;
+  size_t off = 0;
+  bool ok = true;
+  template <typename T>
+  T* take(size_t n) {
+    off = (off + 255) & ~size_t(255);
+    T* p = reinterpret_cast<T*>(base + off);
+    off += std::max<size_t>(n, 1) * sizeof(T);
+    ok = ok && off <= kNaBytes;
+    return p;
+  }
+};
+
 }  // namespace
 
 // ===========================================================================
@@ -1418,6 +1475,158 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
       r.samples_xp = count;
   }
   // the fixed-count estimate of Lemma 2: OI = beta_0 * mean(Y), IS = OI + |S|
+  r.T = count;
+  r.hT = r.sum_y;
+  r.mu = count ? (double)r.sum_y / (double)count : 0.0;
+  r.oi = Q.beta0 > 0.0 && count ? Q.beta0 * r.mu : 0.0;
+  r.is = r.oi + (double)Q.S.size();
+  if (sums) *sums = r;
+  return OI_OK;
+}
+
+oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
+                                  uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out,
+                                  uint64_t* e_out, oi_result* sums) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (stream != 0 && stream != 1) return fail(OI_EINVAL, "stream must be 0 or 1");
+  if (first + count < first || first + count > kMaxSample) return fail(OI_ERANGE, "sample range beyond 2^59");
+  if (count > 0 && !y_out) return fail(OI_EINVAL, "y_out is required");
+  if (g->n > kNaMaxN) return fail(OI_ERANGE, "oi_sample_fixed_noalloc takes graphs of at most 2^22 nodes");
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != g->device) return fail(OI_EINVAL, "call with the graph's device current");
+  char* base = nullptr;
+  OI_TRY(na_scratch(dev, &base));
+  HostQuery Q;
+  Q.qid = query_id;
+  OI_TRY(build_table(g, seeds, k, Q));
+  if (Q.l > kNaMaxL) return fail(OI_ERANGE, "Stage-1 table above 2^18 entries");
+  if ((int64_t)Q.S.size() > kNaMaxK) return fail(OI_ERANGE, "seed set above 2^16 nodes");
+  oi_result r{};
+  r.beta0 = Q.beta0;
+  r.k = (int64_t)Q.S.size();
+  r.l = Q.l;
+  if (Q.beta0 > 0.0 && count > 0) {
+    const int64_t n = g->n;
+    const int64_t words = (n + 31) / 32;
+    const int64_t ng = std::max<int64_t>((Q.l + 3) / 4, 1);
+    Carve c{base};
+    unsigned long long* ctl = c.take<unsigned long long>(16 + 2);  // control block, then (sum Y, sum E)
+    oi::Segment* d_seg = c.take<oi::Segment>(1);
+    oi::QueryDev* d_q = c.take<oi::QueryDev>(1);
+    double* d_cdf = c.take<double>((size_t)Q.l + 1);
+    oi::TabGroup* d_tab = c.take<oi::TabGroup>((size_t)ng);
+    int32_t* d_shash = c.take<int32_t>(Q.shash.size());
+    unsigned long long* list1 = c.take<unsigned long long>(kNaLaunch);
+    unsigned long long* list2 = c.take<unsigned long long>(kNaLaunch);
+    // one block with an n-entry queue for samples that outgrow the main pool
+    uint32_t* gbits = reinterpret_cast<uint32_t*>(c.take<unsigned long long>((size_t)(words + 1) / 2));
+    int32_t* gqueue = c.take<int32_t>((size_t)n);
+    // the main pool: as many blocks as are resident and fit in the rest
+    const int64_t qcap = std::min<int64_t>(n, kNaQcap);
+    const size_t off0 = (c.off + 255) & ~size_t(255);
+    const size_t per = (size_t)words * 4 + (size_t)qcap * 4;
+    int occ = 0;
+    HIP_TRY(oi::large_occupancy(false, &occ));
+    const size_t room = off0 + 1024 < kNaBytes ? kNaBytes - off0 - 1024 : 0;
+    const int blocks = (int)std::min<size_t>((size_t)std::max(occ, 1) * (size_t)g->cus, room / per);
+    if (!c.ok || blocks < 1) return fail(OI_ERANGE, "scratch array too small for this graph and seed set");
+    uint32_t* bits = reinterpret_cast<uint32_t*>(c.take<unsigned long long>(((size_t)blocks * words + 1) / 2));
+    int32_t* queue = c.take<int32_t>((size_t)blocks * (size_t)qcap);
+    if (!c.ok) return fail(OI_ERANGE, "scratch array too small for this graph and seed set");
+    // the Stage-1 table (as upload_query lays it out) and the query
+    std::vector<oi::TabGroup> tab((size_t)ng);
+    std::memset(tab.data(), 0, tab.size() * sizeof(oi::TabGroup));
+    for (int64_t j = 0; j < Q.l; ++j) {
+      tab[j >> 2].v[j & 3] = Q.v[j];
+      tab[j >> 2].thr[j & 3] = Q.thr[j];
+    }
+    oi::QueryDev qd{};
+    qd.cdf = d_cdf;
+    qd.tab = d_tab;
+    qd.shash = d_shash;
+    qd.l = Q.l;
+    qd.smask = Q.smask;
+    qd.k = (int32_t)Q.S.size();
+    qd.s0 = Q.S.size() == 1 ? Q.S[0] : -1;
+    qd.qid = Q.qid;
+    qd.beta0 = Q.beta0;
+    hipStream_t st = g->stream;
+    oi_status status = OI_OK;
+    // every exit below waits for the stream first: the copies read host
+    // memory of this frame
+    auto run = [&]() -> oi_status {
+      HIP_TRY(hipMemcpyAsync(d_tab, tab.data(), tab.size() * sizeof(oi::TabGroup), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(d_cdf, Q.cdf.data(), (size_t)(Q.l + 1) * sizeof(double), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(d_shash, Q.shash.data(), Q.shash.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+      HIP_TRY(hipMemcpyAsync(d_q, &qd, sizeof(qd), hipMemcpyHostToDevice, st));
+      // the bitmaps must start empty (the array keeps whatever the last call left)
+      HIP_TRY(oi::launch_clear_u64(reinterpret_cast<unsigned long long*>(gbits), (uint64_t)(words + 1) / 2, st));
+      HIP_TRY(oi::launch_clear_u64(reinterpret_cast<unsigned long long*>(bits), ((uint64_t)blocks * words + 1) / 2,
+                                   st));
+      for (uint64_t done = 0; done < count;) {
+        const uint64_t cnt = std::min<uint64_t>(count - done, kNaLaunch);
+        oi::Segment sd{};
+        sd.q = 0;
+        sd.stream = (uint32_t)stream;
+        sd.first = first + done;
+        sd.count = cnt;
+        sd.out_off = done;
+        sd.flat0 = 0;
+        HIP_TRY(hipMemcpyAsync(d_seg, &sd, sizeof(sd), hipMemcpyHostToDevice, st));
+        HIP_TRY(oi::launch_clear_u64(ctl, 16 + 2, st));
+        oi::SampleLaunch A = make_launch(g, d_seg, d_q, 1, cnt, run_seed, y_out, e_out, ctl, ctl + 16);
+        A.list1 = list1;
+        A.list2 = list2;
+        A.list3 = list1;  // free once the small kernel has run
+        A.bits = bits;
+        A.queue = queue;
+        A.bits_words = words;
+        A.qcap = (uint32_t)qcap;
+        A.queue_stride = qcap;
+        A.small_direct_max = g->small_direct == 1 ? 0xFFFFFFFFu : (g->small_direct == 2 ? 0u : (uint32_t)blocks);
+        A.nbig = nullptr;
+        A.soft_cap = (uint32_t)qcap;
+        A.soft_budget = 0;
+        OI_TRY(launch_tiers(g, A, false, nullptr, st, blocks));
+        unsigned long long h[18] = {0};
+        HIP_TRY(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if ((h[4] & 0xffffffffull) == 0 && (h[12] & 0xffffffffull) != 0) {
+          // samples that outgrew the main pool's queues: the block with an n-entry queue
+          oi::SampleLaunch B = A;
+          B.list2 = A.list3;
+          B.nlist2 = A.nlist3;
+          B.counter2 = ctl + 13;
+          B.bits = gbits;
+          B.queue = gqueue;
+          B.qcap = (uint32_t)std::min<int64_t>(n, 0xFFFFFFFFll);
+          B.queue_stride = n;
+          B.list3 = nullptr;
+          B.nlist3 = nullptr;
+          B.soft_cap = B.qcap;
+          B.nsoft = nullptr;
+          HIP_TRY(oi::launch_large_full(false, B, 1, st));
+          HIP_TRY(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
+          HIP_TRY(hipStreamSynchronize(st));
+        }
+        const unsigned int err = (unsigned int)(h[4] & 0xffffffffull);
+        if (err) return fail(OI_ESTATE, "sampling kernel reported inconsistency code " + std::to_string(err));
+        r.sum_y += h[16];
+        r.edges_examined += h[17];
+        r.rounds += 1;
+        done += cnt;
+      }
+      return OI_OK;
+    };
+    status = run();
+    (void)hipStreamSynchronize(st);
+    OI_TRY(status);
+    if (stream == 0)
+      r.samples_x = count;
+    else
+      r.samples_xp = count;
+  }
   r.T = count;
   r.hT = r.sum_y;
   r.mu = count ? (double)r.sum_y / (double)count : 0.0;
