@@ -55,6 +55,7 @@ def lib():
         g = [i64, i64, vp, vp, vp]
         L.oo_sample_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, vp, C.c_int]
         L.oo_stage1.argtypes = g + [vp, i64, i64, _P(i64), _P(dbl), vp, vp, vp, vp, _P(i64)]
+        L.oo_mc_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, _P(i64), C.c_int]
         L.oo_selection.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp]
         L.oo_rsa_arrays.argtypes = [vp, u64, vp, u64, dbl, dbl, dbl, dbl, dbl, dbl, _P(RsaResult)]
         L.oo_gsra_array.argtypes = [vp, u64, dbl, dbl, dbl, dbl, dbl, dbl, _P(dbl), _P(u64), _P(u64), _P(dbl)]
@@ -63,7 +64,7 @@ def lib():
                                       _P(i64), _P(RsaResult)]
         L.oo_exact.argtypes = g + [vp, i64, _P(dbl), vp, vp]
         L.oo_backward.argtypes = g + [vp, i64, u32, u32, u64, u64, vp, vp, _P(u64), _P(dbl), C.c_int]
-        for f in ("oo_sample_fixed", "oo_stage1", "oo_selection", "oo_rsa_arrays", "oo_gsra_array", "oo_rsa_plan",
+        for f in ("oo_sample_fixed", "oo_mc_fixed", "oo_stage1", "oo_selection", "oo_rsa_arrays", "oo_gsra_array", "oo_rsa_plan",
                   "oo_estimate", "oo_exact", "oo_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -162,6 +163,28 @@ def sample_fixed(g, seeds, qid: int, seed: int, stream: int, first: int, count: 
     b = float(b0[0])
     oi = b * (int(sums[0]) / count) if (b > 0.0 and count > 0) else 0.0
     return dict(y=y, e=e, sum_y=int(sums[0]), sum_e=int(sums[1]), beta0=b, oi=oi, is_=oi + k)
+
+
+def mc_fixed(g, seeds, qid: int, seed: int, stream: int, first: int, count: int,
+             want_y: bool = True, want_e: bool = False, nthreads: int | None = None):
+    """Classic IC Monte-Carlo samples (Sec. 2.3): per-sample M - |S| (uint32)
+    and E (uint64) of samples first..first+count-1.
+
+    Returns dict(y, e, sum_y, sum_e, k, is_, oi) with the MC_N estimate
+    is_ = |S| + mean(M - |S|) of I(S) and oi = is_ - |S|."""
+    gg = _graph(g)
+    s = _seeds(seeds)
+    y = np.zeros(count, np.uint32) if want_y else None
+    e = np.zeros(count, np.uint64) if want_e else None
+    sums = np.zeros(2, np.uint64)
+    kk = C.c_int64()
+    nt = nthreads_default() if nthreads is None else nthreads
+    rc = lib().oo_mc_fixed(*_gargs(gg), _ptr(s), s.size, qid, seed, stream, first, count,
+                           _ptr(y), _ptr(e), _ptr(sums), C.byref(kk), nt)
+    _chk("mc_fixed", rc)
+    k = kk.value
+    oi = int(sums[0]) / count if count else 0.0
+    return dict(y=y, e=e, sum_y=int(sums[0]), sum_e=int(sums[1]), k=k, oi=oi, is_=k + oi)
 
 
 def selection(g, seeds, qid: int, seed: int, stream: int, first: int, count: int):

@@ -15,7 +15,8 @@
  *     enumeration form of Ext(S) used in the proof of Lemma 1);
  *   - the Stage-1 quantities P_{S,v}, Pr[A_i] and beta_0 (Sec. 3.1,
  *     Eqs. psv, pai, pal, zerop);
- *   - one IICP sample (Alg. 1);
+ *   - one IICP sample (Alg. 1), and one classic IC Monte-Carlo sample M^(S)
+ *     (Sec. 2.3) for comparison;
  *   - GSRA (Alg. 2) and RSA (Alg. 3) over abstract integer streams;
  *   - SOIEA (Alg. 4) and SIEA (Alg. 5, the Z transform of Sec. 5.2);
  *   - a score-function gradient of the fixed-count estimate (not in the
@@ -403,6 +404,115 @@ int oo_sample_fixed(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t 
         off += c;
         if (nthreads == 1) fixed_worker(&jobs[i]);
         else pthread_create(&th[i], NULL, fixed_worker, &jobs[i]);
+    }
+    rc = OO_OK;
+    for (int i = 0; i < nthreads; ++i) {
+        if (nthreads > 1) pthread_join(th[i], NULL);
+        if (jobs[i].rc) rc = jobs[i].rc;
+        sums[0] += jobs[i].sumY;
+        sums[1] += jobs[i].sumE;
+    }
+    free(jobs); free(th);
+    oo_table_free(&t);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Classic IC Monte-Carlo sample M^(S) (Sec. 2.3, Lemma 3)                  */
+/* ------------------------------------------------------------------------ */
+/*
+ * One plain IC cascade from S: every node of S is active from the start, and
+ * a FIFO BFS examines each out-edge (u, v) of each active node once, with
+ * its coin (R4/R5: the same edge coin as an IICP sample with this key uses
+ * in Stage 2).  Returns M - |S|, the number of nodes outside S that end
+ * active (zero allowed); *E_out receives the out-degree summed over every
+ * node expanded, S included.  The visited flags are cleared before
+ * returning.
+ */
+static uint32_t mc_sample(const oo_graph *g, const oo_table *t, uint32_t qid, uint32_t seed,
+                          uint32_t stream, uint64_t s, uint64_t *E_out, oo_scratch *w)
+{
+    int64_t head = 0, tail = 0;
+    uint64_t E = 0;
+    for (int64_t i = 0; i < t->k; ++i) {
+        w->queue[tail++] = t->S[i];
+        w->vis[t->S[i]] = 1;
+    }
+    while (head < tail) {
+        int32_t u = w->queue[head++];
+        int64_t b = g->row_ptr[u], e1 = g->row_ptr[u + 1];
+        E += (uint64_t)(e1 - b);
+        for (int64_t e = b; e < e1; ++e) {
+            int32_t v = g->col[e];
+            if (w->vis[v]) continue;
+            if (edge_coin(qid, seed, stream, s, g, e)) {
+                w->vis[v] = 1;
+                w->queue[tail++] = v;
+            }
+        }
+    }
+    for (int64_t h = 0; h < tail; ++h) w->vis[w->queue[h]] = 0;
+    if (E_out) *E_out = E;
+    return (uint32_t)(tail - t->k);
+}
+
+typedef struct {
+    const oo_graph *g; const oo_table *t;
+    uint32_t qid, seed, stream;
+    uint64_t first, count;
+    uint32_t *y_out; uint64_t *e_out;
+    uint64_t sumY, sumE;
+    int rc;
+} mc_job;
+
+static void *mc_worker(void *arg)
+{
+    mc_job *j = arg;
+    oo_scratch w;
+    if (scratch_init(&w, j->g->n)) { j->rc = OO_ENOMEM; return NULL; }
+    uint64_t sy = 0, se = 0;
+    for (uint64_t q = 0; q < j->count; ++q) {
+        uint64_t E;
+        uint32_t Y = mc_sample(j->g, j->t, j->qid, j->seed, j->stream, j->first + q, &E, &w);
+        if (j->y_out) j->y_out[q] = Y;
+        if (j->e_out) j->e_out[q] = E;
+        sy += Y;
+        se += E;
+    }
+    scratch_free(&w);
+    j->sumY = sy;
+    j->sumE = se;
+    j->rc = OO_OK;
+    return NULL;
+}
+
+/* Oracle entry: `count` classic Monte-Carlo samples M^(S) - |S| of stream
+ * `stream` from index `first`; sums = [sum of M - |S|, sum of E].  The mean of
+ * M over N samples is the MC_N estimate of I(S) (Sec. 6.1). */
+int oo_mc_fixed(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                const float *p, const int32_t *seeds, int64_t k, uint32_t qid,
+                uint32_t seed, uint32_t stream, uint64_t first, uint64_t count,
+                uint32_t *y_out, uint64_t *e_out, uint64_t *sums, int64_t *k_out, int nthreads)
+{
+    oo_graph g = {n, m, row_ptr, col, p};
+    oo_table t;
+    int rc = oo_table_build(&g, seeds, k, &t);
+    if (rc) return rc;
+    if (k_out) *k_out = t.k;
+    sums[0] = sums[1] = 0;
+    if (count == 0) { oo_table_free(&t); return OO_OK; }
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > count) nthreads = (int)count;
+    mc_job *jobs = calloc((size_t)nthreads, sizeof(mc_job));
+    pthread_t *th = calloc((size_t)nthreads, sizeof(pthread_t));
+    uint64_t per = count / (uint64_t)nthreads, rem = count % (uint64_t)nthreads, off = 0;
+    for (int i = 0; i < nthreads; ++i) {
+        uint64_t c = per + ((uint64_t)i < rem ? 1 : 0);
+        jobs[i] = (mc_job){&g, &t, qid, seed, stream, first + off, c,
+                           y_out ? y_out + off : NULL, e_out ? e_out + off : NULL, 0, 0, 0};
+        off += c;
+        if (nthreads == 1) mc_worker(&jobs[i]);
+        else pthread_create(&th[i], NULL, mc_worker, &jobs[i]);
     }
     rc = OO_OK;
     for (int i = 0; i < nthreads; ++i) {
