@@ -133,6 +133,23 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
                           oi_result* sums);
 
 /*
+ * Classic IC Monte-Carlo cascades M^(S) (Sec. 2.3; the MC_N estimators the
+ * paper compares against, Sec. 6.1): samples first .. first+count-1 of stream
+ * `stream`.  Every node of S is active from the start and each out-edge of
+ * each active node is examined once with its coin; a sample shares its edge
+ * coins with the IICP sample of the same key (query_id, run_seed, stream,
+ * index).  y_out: device uint32[count] (or NULL) receives M - |S|, the nodes
+ * outside S that end active (zero allowed); e_out: device uint64[count] (or
+ * NULL) the out-degree summed over every node expanded, S included.  sums
+ * (host, may be NULL): sum_y = sum of M - |S|, edges_examined, k, l, beta0
+ * (of the Stage-1 table, for comparison), and the MC_N estimates over these
+ * samples: is = |S| + mean(M - |S|), oi = is - |S| (mu = oi, T = count).
+ * Samples are drawn even when beta_0 = 0 (they are then all zero).
+ */
+oi_status oi_sample_mc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
+                       uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums);
+
+/*
  * oi_sample_fixed for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * the same samples, outputs and sums as oi_sample_fixed, with no hipMalloc,

@@ -85,6 +85,7 @@ def _load():
         "oi_stage1_table": [vp, vp, i64, i64, P(i64), P(dbl), vp, vp, vp, vp],
         "oi_sample_fixed": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
         "oi_sample_fixed_noalloc": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
+        "oi_sample_mc": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
         "oi_estimate": [vp, u32, vp, i64, dbl, dbl, ci, u32, P(oi_result)],
         "oi_estimate_batch": [vp, i32, vp, vp, vp, dbl, dbl, ci, u32, vp],
         "oi_backward": [vp, u32, vp, i64, u64, u64, u32, vp, ci, dbl, vp],
@@ -207,6 +208,14 @@ def oi_sample_fixed(g, query_id, seeds, stream, first, count, run_seed, y_out=No
     _check("oi_sample_fixed", _lib.oi_sample_fixed(g, int(query_id), _ptr(s), s.size, int(stream), int(first),
                                                     int(count), int(run_seed), _ptr(y_out), _ptr(e_out),
                                                     C.byref(r)))
+    return r.as_dict()
+
+
+def oi_sample_mc(g, query_id, seeds, stream, first, count, run_seed, y_out=None, e_out=None):
+    s = _host(seeds, np.int32)
+    r = oi_result()
+    _check("oi_sample_mc", _lib.oi_sample_mc(g, int(query_id), _ptr(s), s.size, int(stream), int(first),
+                                              int(count), int(run_seed), _ptr(y_out), _ptr(e_out), C.byref(r)))
     return r.as_dict()
 
 

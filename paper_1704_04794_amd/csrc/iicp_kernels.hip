@@ -270,7 +270,10 @@ __device__ __forceinline__ void hand_over(bool pred, uint64_t f, unsigned long l
   }
 }
 
-template <int CAP, bool BWD>
+// MC: the launch's samples are classic Monte-Carlo cascades (Sec. 2.3), a
+// separate instantiation so that the IICP loop carries none of their
+// bookkeeping.
+template <int CAP, bool BWD, bool MC>
 __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   __shared__ int32_t vis_all[4][CAP * 64];
   const int lane = threadIdx.x & 63;
@@ -323,6 +326,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     // rarely meet on one address (the final flush, where they would, is
     // wave-cooperative)
     if (st == T_POP && qh == cnt) {
+      if (MC) --cnt;  // a Monte-Carlo sample does not count its seed
       if (BWD) {
         if (cnt != y) atomicOr(A.err, 2u);
       } else {
@@ -377,7 +381,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
           c_smask = Qp->smask;
           c_shash = Qp->shash;
           c_tab = Qp->tab;
-          if (c_l == 1) {
+          if (!MC && c_l == 1) {
             c_v0 = cptr(c_tab)->v[0];
             c_rb0 = cptr(A.row_ptr)[c_v0];
             c_re0 = cptr(A.row_ptr)[c_v0 + 1];
@@ -421,13 +425,23 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       smask = c_smask;
       shash = c_shash;
       tab = c_tab;
-      pass_on = ql > (int64_t)TINY_LMAX;
+      // a Monte-Carlo sample starts from its seed set, which this kernel
+      // takes only when it is one node (its output is then the visited
+      // count minus that seed)
+      pass_on = MC ? c_k != 1 : ql > (int64_t)TINY_LMAX;
       if (BWD) {
         y = A.y_in[oidx];
         pass_on |= y > (uint32_t)CAP;
       }
       if (pass_on) {
         st = T_IDLE;
+      } else if (MC) {
+        // Sec. 2.3: the seed is active and is expanded first, as any node
+        vis[0] = c_s0;
+        cnt = 1;
+        qh = 0;
+        E = 0;
+        st = T_POP;
       } else if (c_l == 1) {
         // Stage 1 with a single table entry (the selection of Alg. 1 picks it
         // whatever U is, and no entry follows): v_0 is activated and, with
@@ -669,6 +683,7 @@ struct SmallLds {
   uint32_t s_y[K];
   int32_t s_vi[K];
   uint32_t s_i[K];
+  uint32_t s_mc[K];  // 1: a classic Monte-Carlo sample (its seed is counted in s_cnt)
   // the slot's query, copied when the sample starts
   uint32_t s_full;  // slots whose LDS set overflowed (backward consistency check)
   const TabGroup* s_tab[K];
@@ -815,6 +830,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         const uint64_t s = S.first + (f - S.flat0);
         uint32_t y = 0;
         bool start = true;
+        const bool mc = Q.mc != 0;
         if (BWD) {
           y = A.y_in[S.out_off + (f - S.flat0)];
           if (y > CMAX) {  // known too large for LDS: straight to the large kernel
@@ -822,14 +838,24 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
             A.list2[pos] = f;
             start = false;
           }
+        } else if (mc && Q.k != 1) {
+          // a Monte-Carlo sample from several seeds: the large kernel
+          // queues the whole seed set
+          const unsigned int pos = atomicAdd(A.nlist2, 1u);
+          A.list2[pos] = f;
+          start = false;
         }
         if (start) {
-          int64_t i = select_entry(Q, A.seed, S.stream, s);
-          if (i < 0) {
-            atomicOr(A.err, 1u);
-            i = 0;
+          int64_t i = 0;
+          int32_t vi = Q.s0;  // a Monte-Carlo sample starts by expanding its seed (Sec. 2.3)
+          if (!mc) {
+            i = select_entry(Q, A.seed, S.stream, s);
+            if (i < 0) {
+              atomicOr(A.err, 1u);
+              i = 0;
+            }
+            vi = tab_v(Q.tab, i);
           }
-          const int32_t vi = tab_v(Q.tab, i);
           W.s_tab[lane] = Q.tab;
           W.s_shash[lane] = Q.shash;
           W.s_l[lane] = Q.l;
@@ -841,13 +867,14 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
           W.s_q[lane] = S.q;
           W.s_seg[lane] = sg;
           W.s_stream[lane] = S.stream;
-          W.s_E[lane] = (unsigned long long)(Q.l - 1 - i);
+          W.s_E[lane] = mc ? 0ull : (unsigned long long)(Q.l - 1 - i);
           W.s_cnt[lane] = 1;
-          W.s_pend[lane] = (i + 1 < Q.l) ? 2u : 1u;
+          W.s_pend[lane] = (!mc && i + 1 < Q.l) ? 2u : 1u;
           W.s_new[lane] = 0;
           W.s_y[lane] = y;
           W.s_vi[lane] = vi;
           W.s_i[lane] = (uint32_t)i;
+          W.s_mc[lane] = mc ? 1u : 0u;
           W.s_active[lane] = 1;
           if (BWD) atomicAdd(&A.acc_tab[i], (unsigned long long)y);
         } else {
@@ -866,7 +893,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         const int32_t vi = W.s_vi[lane];
         W.hash[lane][hslot<HCAP>(vi)] = vi;
         const uint32_t i = W.s_i[lane];
-        const bool more = (int64_t)i + 1 < W.s_l[lane];
+        const bool more = !W.s_mc[lane] && (int64_t)i + 1 < W.s_l[lane];
         const uint32_t pos = atomicAdd(&W.tail, more ? 2u : 1u);
         W.ring[pos & (RCAP - 1)] = mk_item(lane, ITEM_NODE, 0, (uint32_t)vi);
         if (more) W.ring[(pos + 1) & (RCAP - 1)] = mk_item(lane, ITEM_STAGE1, 0, i + 1);
@@ -1097,7 +1124,7 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       if (uniform(W.s_active[k]) && uniform(W.s_pend[k]) == 0u) {
-        const uint32_t cnt = uniform(W.s_cnt[k]);
+        const uint32_t cnt = uniform(W.s_cnt[k]) - uniform(W.s_mc[k]);
         const uint64_t E = uniform64(W.s_E[k]);
         const uint32_t sg = uniform(W.s_seg[k]);
         if (lane == 0) {
@@ -1251,24 +1278,46 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
     }
     mark_seed_set<NT>(Q, bits, true, tid);
     __syncthreads();
+    const bool mc = !BWD && Q.mc != 0;
     if (tid == 0) {
-      int64_t i = select_entry(Q, A.seed, S.stream, s);
-      if (i < 0) {
-        atomicOr(A.err, 1u);
-        i = 0;
+      if (mc) {
+        // Sec. 2.3: a Monte-Carlo cascade starts with all of S active (its
+        // bits are set above); a single seed is queued here
+        s_tail = 0;
+        if (Q.k == 1) {
+          queue[0] = Q.s0;
+          s_tail = 1;
+        }
+        s_E = 0;
+        s_i = Q.l;
+      } else {
+        int64_t i = select_entry(Q, A.seed, S.stream, s);
+        if (i < 0) {
+          atomicOr(A.err, 1u);
+          i = 0;
+        }
+        const int32_t vi = tab_v(Q.tab, i);
+        queue[0] = vi;
+        atomicOr(&bits[vi >> 5], 1u << (vi & 31));
+        s_tail = 1;
+        s_E = (unsigned long long)(Q.l - 1 - i);
+        s_i = i;
+        if (BWD) atomicAdd(&A.acc_tab[i], y);
       }
-      const int32_t vi = tab_v(Q.tab, i);
-      queue[0] = vi;
-      atomicOr(&bits[vi >> 5], 1u << (vi & 31));
-      s_tail = 1;
-      s_E = (unsigned long long)(Q.l - 1 - i);
-      s_i = i;
-      if (BWD) atomicAdd(&A.acc_tab[i], y);
     }
     __syncthreads();
+    if (mc && Q.k != 1) {
+      // several seeds: every one goes into the queue (from the seed-set table)
+      for (uint32_t h = tid; h <= Q.smask; h += NT) {
+        const int32_t v = gptr(Q.shash)[h];
+        if (v >= 0) push(queue, &s_tail, A.qcap, v);
+      }
+      __syncthreads();
+    }
     const int64_t i = s_i;
-    // Alg. 1, Stage 1: one coin for each later table entry
-    const int64_t gend = (Q.l + 3) >> 2;
+    // Alg. 1, Stage 1: one coin for each later table entry (none for a
+    // Monte-Carlo sample)
+    const int64_t gend = mc ? 0 : (Q.l + 3) >> 2;
     for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += NT) {
       const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
       const TabGroup T = load_tab(Q.tab, g);
@@ -1412,16 +1461,18 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       continue;
     }
     if (tid == 0) {
+      // a Monte-Carlo sample's output leaves out the seeds it started with
+      const uint32_t Yo = mc ? Y - (uint32_t)Q.k : Y;
       if (BWD) {
         if (Y != y) atomicOr(A.err, 2u);
       } else {
-        if (A.y_out) A.y_out[oidx] = Y;
+        if (A.y_out) A.y_out[oidx] = Yo;
         if (A.e_out) A.e_out[oidx] = s_E;
         if (A.nbig && Y > A.big_mark) atomicAdd(A.nbig, 1u);
       }
-      atomicAdd(&A.seg_sums[2 * sg], (unsigned long long)Y);
+      atomicAdd(&A.seg_sums[2 * sg], (unsigned long long)Yo);
       atomicAdd(&A.seg_sums[2 * sg + 1], s_E);
-      atomicAdd(&A.tier_sums[4], (unsigned long long)Y);
+      atomicAdd(&A.tier_sums[4], (unsigned long long)Yo);
       atomicAdd(&A.tier_sums[5], s_E);
     }
     for (uint32_t t = tid; t < Y; t += NT) bits[queue[t] >> 5] = 0u;
@@ -1850,16 +1901,18 @@ int tiny_cap() { return TINY_CAP; }
 hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu) {
   return hipOccupancyMaxActiveBlocksPerMultiprocessor(
       blocks_per_cu,
-      bwd ? reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true>)
-          : reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false>),
+      bwd ? reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true, false>)
+          : reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false>),
       256, 0);
 }
 
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
   if (bwd)
-    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, true>), dim3(blocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, true, false>), dim3(blocks), dim3(256), 0, st, A);
+  else if (A.mc)
+    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false, true>), dim3(blocks), dim3(256), 0, st, A);
   else
-    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false>), dim3(blocks), dim3(256), 0, st, A);
+    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false, false>), dim3(blocks), dim3(256), 0, st, A);
   return hipGetLastError();
 }
 

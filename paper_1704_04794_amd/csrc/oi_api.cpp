@@ -604,6 +604,10 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   oi::SampleLaunch A = make_launch(g, g->d_segs.as<oi::Segment>(), g->d_qs.as<oi::QueryDev>(), (int32_t)ds.size(),
                                    total, seed, y_dev, e_dev, ctl, g->d_sums.as<unsigned long long>());
   const bool is_bwd = bwd != nullptr;
+  // Monte-Carlo queries are never mixed with IICP ones in a launch
+  A.mc = qs.empty() ? 0 : qs[0]->dev.mc;
+  for (const HostQuery* q : qs)
+    if (q->dev.mc != A.mc) return fail(OI_ESTATE, "a launch mixes Monte-Carlo and IICP queries");
   if (is_bwd) {
     // the backward knows every sample's Y, so while the soft cap is on (and
     // the last forward launch had few samples above it) those samples go
@@ -1438,9 +1442,15 @@ oi_status oi_stage1_table(oi_graph* g, const int32_t* seeds, int64_t k, int64_t 
   return OI_OK;
 }
 
-oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
-                          uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out,
-                          oi_result* sums) {
+}  // extern "C"
+
+namespace {
+
+// Fixed-count sampling of IICP samples (mc = false) or of classic IC
+// Monte-Carlo cascades (mc = true), in launches of up to round_max.
+oi_status sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
+                       uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums,
+                       bool mc) {
   if (!g) return fail(OI_EINVAL, "null graph");
   if (stream != 0 && stream != 1) return fail(OI_EINVAL, "stream must be 0 or 1");
   if (first + count < first || first + count > kMaxSample) return fail(OI_ERANGE, "sample range beyond 2^59");
@@ -1452,8 +1462,11 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
   r.beta0 = Q.beta0;
   r.k = (int64_t)Q.S.size();
   r.l = Q.l;
-  if (Q.beta0 > 0.0 && count > 0) {
+  // IICP samples need a non-trivial cascade to exist (beta_0 > 0); a
+  // Monte-Carlo cascade is drawn whatever beta_0 is
+  if ((mc || Q.beta0 > 0.0) && count > 0) {
     OI_TRY(upload_query(g, Q));
+    Q.dev.mc = mc ? 1 : 0;
     uint32_t* ybuf = y_out;
     if (!ybuf) {
       HIP_TRY(g->d_y.ensure((size_t)std::min<uint64_t>(count, g->round_max) * 4));
@@ -1474,14 +1487,34 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
     else
       r.samples_xp = count;
   }
-  // the fixed-count estimate of Lemma 2: OI = beta_0 * mean(Y), IS = OI + |S|
   r.T = count;
   r.hT = r.sum_y;
   r.mu = count ? (double)r.sum_y / (double)count : 0.0;
-  r.oi = Q.beta0 > 0.0 && count ? Q.beta0 * r.mu : 0.0;
+  if (mc) {
+    // the MC_N estimate of I(S): the mean cascade size |S| + mean(M - |S|)
+    r.oi = r.mu;
+  } else {
+    // the fixed-count estimate of Lemma 2: OI = beta_0 * mean(Y)
+    r.oi = Q.beta0 > 0.0 && count ? Q.beta0 * r.mu : 0.0;
+  }
   r.is = r.oi + (double)Q.S.size();
   if (sums) *sums = r;
   return OI_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
+                          uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out,
+                          oi_result* sums) {
+  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, false);
+}
+
+oi_status oi_sample_mc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
+                       uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums) {
+  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, true);
 }
 
 oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,

@@ -49,6 +49,11 @@ struct QueryDev {
   int32_t s0;            // the seed when k == 1
   uint32_t qid;          // Philox key word 0
   double beta0;
+  // 1: the samples are classic IC Monte-Carlo cascades M^(S) (Sec. 2.3):
+  // no Stage 1, every node of S active from the start, Y = the nodes
+  // outside S that end active (zero allowed); 0: IICP samples (Alg. 1)
+  int32_t mc;
+  int32_t pad;
 };
 
 // A contiguous range of samples of one query's stream.  Samples of all
@@ -129,6 +134,9 @@ struct SampleLaunch {
   uint32_t soft_cap;
   uint32_t soft_budget;
   unsigned int* nsoft;
+  // 1: every query of the launch draws classic Monte-Carlo cascades
+  // (QueryDev::mc), which the tiny kernel runs in an instantiation of its own
+  int32_t mc;
 };
 
 // Hash used for the per-query seed set table (built on the host, probed on the device).
