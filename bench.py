@@ -30,6 +30,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -76,6 +78,25 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def host_info():
+    """CPU model, logical CPUs and RAM of the host the oracle runs on."""
+    model, ram = None, None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+        with open("/proc/meminfo") as f:
+            for line in f:
+                if line.startswith("MemTotal"):
+                    ram = round(int(line.split()[1]) / 2**20, 1)
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "host_logical_cpus": os.cpu_count(), "ram_gib": ram}
+
+
 def cpu_baseline(g, S, seconds):
     import oracle as O
     from oi_inputs.configs import RUN_SEED
@@ -94,7 +115,7 @@ def cpu_baseline(g, S, seconds):
     t = time.perf_counter()
     O.sample_fixed(g, S, 0, RUN_SEED, 0, 0, n1, want_y=False, nthreads=1)
     dt1 = time.perf_counter() - t
-    return {"value": N / dt, "unit": "samples/s", "cores": nt, "kind": "oracle",
+    return {"value": N / dt, "unit": "samples/s", "cores": nt, "kind": "oracle", **host_info(),
             "sample": f"IICP samples 0..{N - 1} of stream X of the same query (fixed count, oracle in C, "
                       f"{nt} threads), {dt:.1f} s; GTEPS {r['sum_e'] / dt / 1e9:.4f}; one thread: "
                       f"{n1} samples in {dt1:.1f} s",
@@ -244,10 +265,12 @@ def billion_edge(P, args):
     return out
 
 
-def batched_vs_single(P, args):
+def batched_vs_single(P, args, per_stratum=False):
     """Seed-set estimates/s on the 4M-node weighted-cascade workload: a seeded
     stratified subset of its 4,096 seed sets (equal numbers from the uniform
-    and the top-1% halves), estimated in one batched call and one at a time."""
+    and the top-1% halves), estimated in one batched call and one at a time
+    (with per_stratum, each half in a batched call of its own, so that the
+    two kinds of seed set are timed apart)."""
     import numpy as np
 
     from oi_inputs import make_config
@@ -275,15 +298,35 @@ def batched_vs_single(P, args):
     torch.cuda.synchronize()
     # both passes with HIP-event kernel timing on (same cost for both)
     G.timing(True)
-    t = time.perf_counter()
-    batch = G.estimate_batch(sub, eps, delta, query_ids=qids)
-    tb = time.perf_counter() - t
+    strata = {}
+    if per_stratum:
+        batch, tb = [], 0.0
+        for name, lo in (("uniform", 0), ("top1pct", k)):
+            t = time.perf_counter()
+            batch += G.estimate_batch(sub[lo:lo + k], eps, delta, query_ids=qids[lo:lo + k])
+            dt = time.perf_counter() - t
+            tb += dt
+            strata[name] = {"sets": k, "batched_s": dt, "batched_estimates_per_s": k / dt}
+            log(f"batched {name}: {k} sets in {dt:.2f}s")
+    else:
+        t = time.perf_counter()
+        batch = G.estimate_batch(sub, eps, delta, query_ids=qids)
+        tb = time.perf_counter() - t
     tm = G.timing()
     log(f"batched: {len(sub)} sets in {tb:.2f}s")
     G.timing(True)
-    t = time.perf_counter()
-    single = [G.estimate(S, eps, delta, query_id=int(q)) for S, q in zip(sub, qids)]
-    ts = time.perf_counter() - t
+    single, ts = [], 0.0
+    for j, (S, q) in enumerate(zip(sub, qids)):
+        t = time.perf_counter()
+        single.append(G.estimate(S, eps, delta, query_id=int(q)))
+        dt = time.perf_counter() - t
+        ts += dt
+        if per_stratum:
+            st = strata["uniform" if j < k else "top1pct"]
+            st["single_s"] = st.get("single_s", 0.0) + dt
+    for st in strata.values():
+        st["single_estimates_per_s"] = st["sets"] / st["single_s"]
+        st["speedup"] = st["single_s"] / st["batched_s"]
     G.timing(False)
     log(f"one at a time: {len(sub)} sets in {ts:.2f}s")
     # the large-cascade kernel of the batched pass against the random-read
@@ -304,7 +347,8 @@ def batched_vs_single(P, args):
             f"({k} uniform + {k} top-1% out-degree, |S| in [1,1000]), SOIEA eps={eps} delta={delta}",
             "batched_estimates_per_s": len(sub) / tb, "single_estimates_per_s": len(sub) / ts,
             "speedup": ts / tb, "identical_results": same, "samples": samples,
-            "batched_samples_per_s": samples / tb, "large_kernel": large, "autotune": tune}
+            "batched_samples_per_s": samples / tb, "large_kernel": large, "autotune": tune,
+            **({"strata": strata} if per_stratum else {})}
 
 
 def batched_vs_single_small(P, args):
@@ -347,6 +391,29 @@ def batched_vs_single_small(P, args):
             "rounds_per_estimate": sum(r["rounds"] for r in single) / q}
 
 
+def seed_spread(P, G, g, eps, delta, count):
+    """One complete estimate for each of `count` seeded single-node seed sets
+    (uniform over nodes with out-degree >= 1; the first is the headline's):
+    the throughput spread over seed sets, with each set's Stage-1 size l."""
+    from oi_inputs import seed_node_outdeg_ge1
+    from oi_inputs.configs import CONFIGS
+    rows = []
+    seeds = [100 + CONFIGS["cl1m"]["number"]] + [1000 + i for i in range(count - 1)]
+    for qi, sd in enumerate(seeds):
+        S = seed_node_outdeg_ge1(g, sd)
+        G.estimate(S, 0.5, delta, query_id=qi)  # warm: table and workspaces
+        t = time.perf_counter()
+        r = G.estimate(S, eps, delta, query_id=qi)
+        dt = time.perf_counter() - t
+        n = r["samples_x"] + r["samples_xp"]
+        rows.append({"seed_node": int(S[0]), "l": r["l"], "samples": n, "seconds": dt, "samples_per_s": n / dt,
+                     "gteps": r["edges_examined"] / dt / 1e9, "mean_y": r["sum_y"] / max(n, 1), "oi": r["oi"]})
+        log(f"spread {qi}: {rows[-1]}")
+    v = np.array([x["samples_per_s"] for x in rows])
+    return {"sets": rows, "samples_per_s_min": float(v.min()), "samples_per_s_median": float(np.median(v)),
+            "samples_per_s_max": float(v.max())}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -366,6 +433,11 @@ def main():
                     help="cl4m: seed sets in the subset (default 32); er2k: seed sets (default 256)")
     ap.add_argument("--no-autotune", action="store_true", help="cl4m: keep the default sampler schedule")
     ap.add_argument("--eps", type=float, default=-1.0, help="cl4m: eps (default: the workload's 0.1)")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="cl1m: skip the batched-vs-single block (er2k and the 4M-node subset)")
+    ap.add_argument("--batched-per-stratum", type=int, default=16,
+                    help="cl1m: seed sets per stratum (uniform, top-1%%) of the 4M-node subset")
+    ap.add_argument("--spread", type=int, default=8, help="cl1m: seed sets of the headline's spread")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device with torch (a plain copy kernel of known size, "
                          "to scale hardware byte counters)")
@@ -465,6 +537,7 @@ def main():
         "sampler": {k: tm[k] for k in ("tiny_ms", "small_ms", "large_ms", "samples", "handed_small",
                                        "handed_large", "tiny_y", "small_y", "large_y")},
     }
+    out["spread"] = seed_spread(P, G, g, eps, delta, args.spread)
     gr = gather_roofline(G)
     out["roofline"]["measured_gather_gbps"] = gr["gbps"]
     out["roofline"]["frac_of_measured_gather"] = achieved / gr["gbps"] if gr["gbps"] > 0 else None
@@ -474,6 +547,17 @@ def main():
         out["backward"] = backward_ratio(P)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, S, args.cpu_seconds)
+    if not args.no_batched:
+        # the metric's second half: seed-set estimates/s batched vs one at a
+        # time at eps = 0.05, where single queries leave the GPU idle (er2k)
+        # and on the 4M-node workload's stratified subset
+        a = argparse.Namespace(**vars(args))
+        a.queries, a.eps = 256, 0.05
+        small = batched_vs_single_small(P, a)
+        a.queries, a.eps = 2 * args.batched_per_stratum, 0.05
+        big = batched_vs_single(P, a, per_stratum=True)
+        big.pop("autotune", None)
+        out["batched"] = {"er2k": small, "cl4m": big}
     print(json.dumps(out), flush=True)
 
 

@@ -144,6 +144,31 @@ def test_cl1m_sigmoid_workload(P):
     G.close()
 
 
+def test_cl1m_sig_theta_full_size(P):
+    """The differentiation workload as configured: forward OI from 10^6 IICP
+    samples and dOI/dtheta over all m edges, every edge against the fp64
+    oracle on the same keys (its dOI/dp times dp/dtheta = p (1 - p))."""
+    import torch
+    g, sets, extra = make_config("cl1m_sig")
+    S = sets[0]
+    N = extra["samples"]
+    G = P.Graph.from_inputs(g)
+    G.set_theta(torch.from_numpy(extra["theta"]).cuda())
+    p = G.probs()
+    h = g.with_p(p)
+    print(f"[gpu] backward cl1m_sig theta N={N} |S|={len(S)}", flush=True)
+    y, _, r = G.sample_fixed(S, N)
+    gt = _gpu_grad(P, G, S, N, param=P.OI_PARAM_THETA, y_in=y)
+    o = O.sample_fixed(h, S, 0, RUN_SEED, 0, 0, N, want_y=False)
+    assert r["oi"] == o["oi"] and r["sum_y"] == o["sum_y"]
+    og, _ = _oracle_grad(h, S, N)
+    pp = p.astype(np.float64)
+    ref = og * pp * (1.0 - pp)
+    assert _rel_l2(gt, ref) <= REL_L2, _rel_l2(gt, ref)
+    _per_edge(gt, ref)
+    G.close()
+
+
 def test_autograd_function(P):
     import torch
     from paper_1704_04794_amd.autograd import outward_influence
