@@ -272,6 +272,24 @@ oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
  * do not depend on the mode.  Errors: OI_EINVAL for a null graph or a mode
  * outside 0..2. */
 oi_status oi_set_pipeline(oi_graph* g, int mode);
+/* Stage-1 skip sampling (part of the sampling specification; results depend
+ * on it).  A Stage-1 table of l >= max(min_l, 65) entries (default min_l =
+ * 4096) is sampled after the selection i (Alg. 1, Stage 1) without one coin
+ * per entry: entries with P_j >= 1/2 keep their coins (kind 2); entries with
+ * 0 < P_j < 1/2 are found by one walk per segment of 256 table indices.  In
+ * segment m (indices [256m, 256m + 256)) R_j is the product of (1 - P_k) over
+ * its entries k <= j with 0 < P_k < 1/2 (fp64, ascending k).  A walk stands
+ * at pos = i if i lies in the segment, else at 256m - 1 with R = 1; it draws
+ * U' = 1 - U with U the 53-bit uniform of Philox (kind 3, idx = pos, or
+ * 2^40 + m at the segment's start), and the next live entry is the smallest
+ * j > pos in the segment with R_j < U' * R_pos; the walk moves to j (idx = j)
+ * and draws again, and ends when no such j exists.  Every later entry is
+ * then live independently with probability P_j, as with one coin each, while
+ * a sample draws about (l - i)/256 + sum_j P_j numbers instead of l - i.  The
+ * examined-edge count still includes the l - 1 - i entries after i.
+ * Applies to calls made after it; min_l < 1 gives OI_EINVAL. */
+oi_status oi_set_stage1_skip(oi_graph* g, int64_t min_l);
+
 /* What oi_autotune chose and measured. */
 typedef struct {
   int32_t variant;      /* small-kernel variant */

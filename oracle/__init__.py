@@ -52,6 +52,8 @@ def lib():
         vp = C.c_void_p
         L.oo_philox.argtypes = [vp, vp, vp]
         L.oo_philox.restype = None
+        L.oo_set_stage1_skip.argtypes = [i64]
+        L.oo_set_stage1_skip.restype = None
         g = [i64, i64, vp, vp, vp]
         L.oo_sample_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, vp, C.c_int]
         L.oo_stage1.argtypes = g + [vp, i64, i64, _P(i64), _P(dbl), vp, vp, vp, vp, _P(i64)]
@@ -117,6 +119,12 @@ def philox(ctr, key):
     out = np.zeros(4, dtype=np.uint32)
     lib().oo_philox(_ptr(c), _ptr(k), _ptr(out))
     return out
+
+
+def set_stage1_skip(min_l: int):
+    """Tables of at least max(min_l, 65) entries use Stage-1 skip sampling
+    (the default min_l is 4096); a process-wide setting of the oracle."""
+    lib().oo_set_stage1_skip(int(min_l))
 
 
 def stage1(g, seeds, cap: int = 1 << 24):

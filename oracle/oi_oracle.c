@@ -57,6 +57,22 @@
  *       sum of squared differences of Y'.
  *   R12 beta_0 = 0 (S has no out-neighbour outside S): OI = 0, IS = |S|, no
  *       samples are drawn.
+ *   R16 Stage-1 skip sampling (a different consumption of randomness for the
+ *       same law, used when l >= max(skip_min_l, 65); skip_min_l = 4096 unless
+ *       set): after the selection i, entries with P_j >= 1/2 ("heavy") are
+ *       flipped with their own coins as in R4; entries with 0 < P_j < 1/2
+ *       ("light") are visited by one walk per segment of 256 table indices.
+ *       Within segment m (indices [256m, 256m + 256)) R_j is the product of
+ *       (1 - P_k) over the light k in [256m, j].  A walk stands at pos = i if
+ *       i lies in the segment, else at 256m - 1 (R = 1 there), draws
+ *       U' = 1 - U (U as for the selection, kind 3, idx = pos, or 2^40 + m at
+ *       the segment's start), and the next live entry is the smallest j > pos
+ *       in the segment with R_j < U' R_pos (none: the walk ends); the walk
+ *       moves to j and draws again.  Given the walk at pos, no entry of
+ *       (pos, j] is live with probability R_j / R_pos, so every light entry
+ *       after i is live independently with probability P_j, while the draws
+ *       number about (l - i) / 256 + sum of P_j instead of l - i.  The
+ *       examined-edge count keeps the l - 1 - i Stage-1 entries of R15.
  */
 #include <math.h>
 #include <pthread.h>
@@ -67,7 +83,12 @@
 typedef unsigned __int128 oo_u128;
 
 enum { OO_OK = 0, OO_EINVAL = -1, OO_ERANGE = -2, OO_ENOMEM = -3 };
-enum { KIND_EDGE = 0, KIND_SELECT = 1, KIND_STAGE1 = 2 };
+enum { KIND_EDGE = 0, KIND_SELECT = 1, KIND_STAGE1 = 2, KIND_SKIP = 3 };
+
+/* R16: the spec's constants and the table size from which skip sampling is used */
+enum { SKIP_SEG = 256, SKIP_LMIN_FLOOR = 65 };
+static int64_t g_skip_min_l = 4096;
+void oo_set_stage1_skip(int64_t min_l) { g_skip_min_l = min_l; }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, from the published description (multiply-xor rounds with  */
@@ -137,13 +158,17 @@ typedef struct {
     double beta0;
     int64_t *se_off;    /* l+1: S-edges into v_j are se[se_off[j]..se_off[j+1]) */
     int64_t *se;        /* edge ids, ascending inside each entry */
+    int skip;           /* R16: Stage 1 by skip sampling */
+    double *R;          /* R16: survival products of light entries, per segment */
+    int64_t *heavy;     /* R16: entries with P_j >= 1/2, ascending */
+    int64_t nheavy;
 } oo_table;
 
 void oo_table_free(oo_table *t)
 {
     if (!t) return;
     free(t->S); free(t->inS); free(t->v); free(t->P); free(t->cdf);
-    free(t->thr); free(t->se_off); free(t->se);
+    free(t->thr); free(t->se_off); free(t->se); free(t->R); free(t->heavy);
     memset(t, 0, sizeof(*t));
 }
 
@@ -235,6 +260,20 @@ int oo_table_build(const oo_graph *g, const int32_t *seeds, int64_t k, oo_table 
         Q = Q * (1.0 - t->P[j]);
     }
     t->beta0 = t->cdf[l];
+    /* R16 */
+    t->skip = l >= (g_skip_min_l > SKIP_LMIN_FLOOR ? g_skip_min_l : SKIP_LMIN_FLOOR);
+    if (t->skip) {
+        t->R = malloc(sizeof(double) * (size_t)l);
+        t->heavy = malloc(sizeof(int64_t) * (size_t)l);
+        if (!t->R || !t->heavy) { oo_table_free(t); return OO_ENOMEM; }
+        double R = 1.0;
+        for (j = 0; j < l; ++j) {
+            if (j % SKIP_SEG == 0) R = 1.0;
+            if (t->P[j] >= 0.5) t->heavy[t->nheavy++] = j;
+            else if (t->P[j] > 0.0) R = R * (1.0 - t->P[j]);
+            t->R[j] = R;
+        }
+    }
     return OO_OK;
 }
 
@@ -244,16 +283,20 @@ int oo_table_build(const oo_graph *g, const int32_t *seeds, int64_t k, oo_table 
 typedef struct {
     uint8_t *vis;     /* n flags, all zero between samples */
     int32_t *queue;   /* n entries */
+    uint8_t *live;    /* Stage-1 live flags of the last sample (table size) */
+    int64_t nlive;
 } oo_scratch;
 
 static int scratch_init(oo_scratch *w, int64_t n)
 {
     w->vis = calloc((size_t)n, 1);
     w->queue = malloc(sizeof(int32_t) * (size_t)(n ? n : 1));
+    w->live = NULL;
+    w->nlive = 0;
     if (!w->vis || !w->queue) { free(w->vis); free(w->queue); return OO_ENOMEM; }
     return OO_OK;
 }
-static void scratch_free(oo_scratch *w) { free(w->vis); free(w->queue); }
+static void scratch_free(oo_scratch *w) { free(w->vis); free(w->queue); free(w->live); }
 
 /* R6: Alg. 1, Stage 1: the first activated table entry */
 static int64_t select_first(const oo_table *t, double U)
@@ -270,12 +313,17 @@ static int64_t select_first(const oo_table *t, double U)
     return -1;
 }
 
+static double uniform53(const uint32_t r[4])
+{
+    uint64_t a = r[0] >> 5, b = r[1] >> 6;
+    return (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
+}
+
 static double selection_uniform(uint32_t qid, uint32_t seed, uint32_t stream, uint64_t s)
 {
     uint32_t r[4];
     draw(qid, seed, KIND_SELECT, stream, s, 0, r);
-    uint64_t a = r[0] >> 5, b = r[1] >> 6;
-    return (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
+    return uniform53(r);
 }
 
 static int stage1_coin(uint32_t qid, uint32_t seed, uint32_t stream, uint64_t s,
@@ -292,6 +340,47 @@ static int edge_coin(uint32_t qid, uint32_t seed, uint32_t stream, uint64_t s,
     uint32_t r[4];
     draw(qid, seed, KIND_EDGE, stream, s, (uint64_t)e >> 2, r);
     return (uint64_t)r[e & 3] < coin_threshold((double)g->p[e]);
+}
+
+/* Alg. 1, Stage 1 after the selection of entry i: which later entries are
+ * live, each with probability P_j (R4, or R16 for long tables).  live[j] is
+ * set to 1 for every live j > i (live has l entries, zero on entry for
+ * j > i). */
+static void stage1_later(const oo_table *t, uint32_t qid, uint32_t seed, uint32_t stream, uint64_t s,
+                         int64_t i, uint8_t *live)
+{
+    if (!t->skip) {
+        for (int64_t j = i + 1; j < t->l; ++j)
+            if (stage1_coin(qid, seed, stream, s, t, j)) live[j] = 1;
+        return;
+    }
+    /* heavy entries: their own coins */
+    for (int64_t h = 0; h < t->nheavy; ++h) {
+        int64_t j = t->heavy[h];
+        if (j > i && stage1_coin(qid, seed, stream, s, t, j)) live[j] = 1;
+    }
+    /* light entries: one walk per segment that reaches past i */
+    for (int64_t m = (i + 1) / SKIP_SEG; m * SKIP_SEG < t->l; ++m) {
+        int64_t a = m * SKIP_SEG, b = a + SKIP_SEG < t->l ? a + SKIP_SEG : t->l;
+        int64_t pos = i >= a ? i : a - 1;
+        double Rpos = pos >= a ? t->R[pos] : 1.0;
+        uint64_t idx = pos >= a ? (uint64_t)pos : (1ull << 40) + (uint64_t)m;
+        for (;;) {
+            uint32_t r[4];
+            draw(qid, seed, KIND_SKIP, stream, s, idx, r);
+            double thr = (1.0 - uniform53(r)) * Rpos;
+            int64_t lo = pos + 1, hi = b;      /* first j in (pos, b) with R_j < thr */
+            while (lo < hi) {
+                int64_t mid = lo + (hi - lo) / 2;
+                if (t->R[mid] < thr) hi = mid; else lo = mid + 1;
+            }
+            if (lo >= b) break;
+            live[lo] = 1;
+            pos = lo;
+            Rpos = t->R[lo];
+            idx = (uint64_t)lo;
+        }
+    }
 }
 
 /*
@@ -315,9 +404,17 @@ static uint32_t iicp_sample(const oo_graph *g, const oo_table *t, uint32_t qid,
     uint64_t E = (uint64_t)(t->l - 1 - i);
     w->queue[tail++] = t->v[i];
     w->vis[t->v[i]] = 1;
-    /* Stage 1: one coin for each later entry j > i */
+    /* Stage 1: each later entry j > i live with probability P_j */
+    if (w->nlive < t->l) {
+        free(w->live);
+        w->live = malloc((size_t)t->l);
+        if (!w->live) abort();   /* a test tool: fail loudly rather than sample wrongly */
+        w->nlive = t->l;
+    }
+    memset(w->live, 0, (size_t)t->l);
+    stage1_later(t, qid, seed, stream, s, i, w->live);
     for (int64_t j = i + 1; j < t->l; ++j) {
-        if (stage1_coin(qid, seed, stream, s, t, j)) {
+        if (w->live[j]) {
             w->queue[tail++] = t->v[j];
             w->vis[t->v[j]] = 1;
             ++Y;
@@ -805,7 +902,7 @@ int oo_estimate(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col
     double a, b, scale, offset;
     if (mode == 0) { a = 1.0; b = nk; scale = 1.0; offset = 0.0; }
     else { a = kd + t.beta0; b = kd + t.beta0 * nk; scale = t.beta0; offset = kd; }
-    iicp_ctx c = {&g, &t, qid, seed, {0, 0}, 0};
+    iicp_ctx c = {&g, &t, qid, seed, {0, 0, 0, 0}, 0};
     if (scratch_init(&c.w, n)) { oo_table_free(&t); return OO_ENOMEM; }
     if (!(b > a)) {
         /* n-|S| = 1 (SOIEA) or beta_0 (n-|S|-1) = 0: Y is always 1 (Lemma 2) */
@@ -952,7 +1049,7 @@ static void *bwd_worker(void *arg)
         }
         /* Stage-1 node coins, mapped to the S-edges into each entry */
         for (int64_t j = 0; j < t->l; ++j) {
-            int xj = (j == i) || (j > i && stage1_coin(b->qid, b->seed, 0, s, t, j));
+            int xj = (j == i) || (j > i && w.live[j]);
             for (int64_t a = t->se_off[j]; a < t->se_off[j + 1]; ++a) {
                 int64_t e = t->se[a];
                 double sc;

@@ -96,6 +96,7 @@ def _load():
         "oi_gather_probe": [vp, u64, u32, P(u64), P(u64), P(dbl)],
         "oi_set_routing": [vp, ci, i64],
         "oi_set_pipeline": [vp, ci],
+        "oi_set_stage1_skip": [vp, i64],
         "oi_autotune": [vp, i32, vp, vp, vp, u64, u32, P(oi_autotune_result)],
     }
     for name, args in sig.items():
@@ -271,6 +272,11 @@ def oi_set_tuning(g, variant=-1, chunk=-1, tiny=-1, tiny_chunk=-1, round_max=-1)
 
 def oi_set_routing(g, small_direct=-1, large_qcap=-1):
     _check("oi_set_routing", _lib.oi_set_routing(g, int(small_direct), int(large_qcap)))
+
+
+def oi_set_stage1_skip(g, min_l):
+    """Stage-1 tables of at least max(min_l, 65) entries use skip sampling."""
+    _check("oi_set_stage1_skip", _lib.oi_set_stage1_skip(g, int(min_l)))
 
 
 def oi_set_pipeline(g, mode):

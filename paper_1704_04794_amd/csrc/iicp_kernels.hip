@@ -109,6 +109,17 @@ __device__ __forceinline__ int32_t tab_v(const TabGroup* base, int64_t j) {
   return *(const OI_GLOBAL int32_t*)(p + 4 * (j & 3));
 }
 
+// coin threshold of Stage-1 entry j
+__device__ __forceinline__ uint64_t tab_thr(const TabGroup* base, int64_t j) {
+  const OI_GLOBAL char* p = (const OI_GLOBAL char*)(gptr(base) + (j >> 2));
+  return *(const OI_GLOBAL uint64_t*)(p + 16 + 8 * (j & 3));
+}
+
+// word k (0..3) of a Philox block, k chosen at run time
+__device__ __forceinline__ uint32_t word_at(const Words& d, int64_t k) {
+  return k == 0 ? d.w[0] : k == 1 ? d.w[1] : k == 2 ? d.w[2] : d.w[3];
+}
+
 // Live iff word < floor(p * 2^32); p = 1 (threshold kThrAlways) is always
 // live.  See coin_threshold.
 __device__ __forceinline__ bool edge_live(uint32_t word, uint32_t thr) {
@@ -833,14 +844,16 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
         const bool mc = Q.mc != 0;
         if (BWD) {
           y = A.y_in[S.out_off + (f - S.flat0)];
-          if (y > CMAX) {  // known too large for LDS: straight to the large kernel
+          // known too large for LDS, or a table sampled by skip sampling
+          // (the large kernel's): straight to the large kernel
+          if (y > CMAX || Q.skip) {
             const unsigned int pos = atomicAdd(A.nlist2, 1u);
             A.list2[pos] = f;
             start = false;
           }
-        } else if (mc && Q.k != 1) {
-          // a Monte-Carlo sample from several seeds: the large kernel
-          // queues the whole seed set
+        } else if (mc ? Q.k != 1 : Q.skip != 0) {
+          // a Monte-Carlo sample from several seeds (the large kernel queues
+          // the whole seed set), or a long table's skip-sampled Stage 1
           const unsigned int pos = atomicAdd(A.nlist2, 1u);
           A.list2[pos] = f;
           start = false;
@@ -1315,9 +1328,63 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       __syncthreads();
     }
     const int64_t i = s_i;
+    const bool skip = !mc && Q.skip != 0;
+    if (skip) {
+      // Alg. 1, Stage 1 by skip sampling (long tables).  Heavy entries
+      // (P >= 1/2) after i: their own coins, one thread each
+      const OI_GLOBAL int32_t* hv = gptr(Q.heavy);
+      int64_t lo = 0, hi = Q.nheavy;  // first heavy entry after i
+      while (lo < hi) {
+        const int64_t mid = (lo + hi) >> 1;
+        if ((int64_t)hv[mid] > i)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      for (int64_t h = lo + tid; h < Q.nheavy; h += NT) {
+        const int64_t j = hv[h];
+        const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)(j >> 2));
+        if ((uint64_t)word_at(d, j & 3) < tab_thr(Q.tab, j)) {
+          if (BWD) atomicAdd(&A.acc_tab[j], y);
+          const int32_t v = tab_v(Q.tab, j);
+          if (claim(bits, v)) push(queue, &s_tail, A.qcap, v);
+        }
+      }
+      // light entries: one walk per segment reaching past i, one thread each.
+      // Standing at pos, the next live entry is the first j > pos of the
+      // segment with R_j < U' R_pos (U' = 1 - U, U a 53-bit uniform).
+      const OI_GLOBAL double* R = gptr(Q.skipR);
+      for (int64_t m = (i + 1) / kSkipSeg + tid; m * kSkipSeg < Q.l; m += NT) {
+        const int64_t a = m * kSkipSeg, b = a + kSkipSeg < Q.l ? a + kSkipSeg : Q.l;
+        int64_t pos = i >= a ? i : a - 1;
+        double Rpos = pos >= a ? R[pos] : 1.0;
+        uint64_t idx = pos >= a ? (uint64_t)pos : (1ull << 40) + (uint64_t)m;
+        while (true) {
+          const Words d = philox_draw(Q.qid, A.seed, KIND_SKIP, S.stream, s, idx);
+          const uint64_t ua = d.w[0] >> 5, ub = d.w[1] >> 6;
+          const double U = (double)(ua * 67108864ull + ub) * (1.0 / 9007199254740992.0);
+          const double thr = (1.0 - U) * Rpos;
+          int64_t jl = pos + 1, jh = b;  // first j in (pos, b) with R_j < thr
+          while (jl < jh) {
+            const int64_t mid = (jl + jh) >> 1;
+            if (R[mid] < thr)
+              jh = mid;
+            else
+              jl = mid + 1;
+          }
+          if (jl >= b) break;
+          if (BWD) atomicAdd(&A.acc_tab[jl], y);
+          const int32_t v = tab_v(Q.tab, jl);
+          if (claim(bits, v)) push(queue, &s_tail, A.qcap, v);
+          pos = jl;
+          Rpos = R[jl];
+          idx = (uint64_t)jl;
+        }
+      }
+    }
     // Alg. 1, Stage 1: one coin for each later table entry (none for a
-    // Monte-Carlo sample)
-    const int64_t gend = mc ? 0 : (Q.l + 3) >> 2;
+    // Monte-Carlo sample or a skip-sampled table)
+    const int64_t gend = (mc || skip) ? 0 : (Q.l + 3) >> 2;
     for (int64_t g = ((i + 1) >> 2) + tid; g < gend; g += NT) {
       const Words d = philox_draw(Q.qid, A.seed, KIND_STAGE1, S.stream, s, (uint64_t)g);
       const TabGroup T = load_tab(Q.tab, g);

@@ -211,6 +211,9 @@ struct oi_graph {
   bool soft_bwd = false;            // the backward may send samples above the soft cap to the full-queue pass
   int variant = 0;
   bool use_tiny = true;
+  // Stage-1 tables of at least max(skip_min_l, 65) entries are sampled by
+  // skip sampling (part of the sampling specification, see oi_set_stage1_skip)
+  int64_t skip_min_l = 4096;
   uint32_t chunk = 256;
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
   // samples per sampling launch (set at creation from free memory, at most
@@ -244,7 +247,12 @@ struct HostQuery {
   std::vector<int64_t> se_off, se;  // S-edges into each entry, ascending edge id
   std::vector<int32_t> shash;
   uint32_t smask = 0;
-  DevBuf d_cdf, d_tab, d_shash;
+  // Stage-1 skip sampling (long tables): survival products of the light
+  // entries per segment and the heavy entries
+  bool skip = false;
+  std::vector<double> R;
+  std::vector<int32_t> heavy;
+  DevBuf d_cdf, d_tab, d_shash, d_R, d_heavy;
   oi::QueryDev dev{};
 };
 
@@ -294,6 +302,24 @@ oi_status build_table(const oi_graph* g, const int32_t* seeds, int64_t k, HostQu
     rest = rest * (1.0 - Q.P[j]);
   }
   Q.beta0 = Q.cdf[Q.l];
+  // Stage-1 skip sampling for long tables: heavy entries (P >= 1/2) keep
+  // their coins; light ones (0 < P < 1/2) are found by walks over the
+  // products of (1 - P) within segments of kSkipSeg entries
+  Q.skip = Q.l >= std::max<int64_t>(g->skip_min_l, oi::kSkipMinFloor);
+  Q.R.clear();
+  Q.heavy.clear();
+  if (Q.skip) {
+    Q.R.resize(Q.l);
+    double R = 1.0;
+    for (int64_t j = 0; j < Q.l; ++j) {
+      if (j % oi::kSkipSeg == 0) R = 1.0;
+      if (Q.P[j] >= 0.5)
+        Q.heavy.push_back((int32_t)j);
+      else if (Q.P[j] > 0.0)
+        R = R * (1.0 - Q.P[j]);
+      Q.R[j] = R;
+    }
+  }
   // open-addressing set of S for the device
   uint32_t cap = 2;
   while (cap < 2 * Q.S.size()) cap <<= 1;
@@ -330,6 +356,17 @@ oi_status upload_query(oi_graph* g, HostQuery& Q) {
   Q.dev.s0 = Q.S.size() == 1 ? Q.S[0] : -1;
   Q.dev.qid = Q.qid;
   Q.dev.beta0 = Q.beta0;
+  Q.dev.skip = Q.skip ? 1 : 0;
+  Q.dev.nheavy = (int64_t)Q.heavy.size();
+  if (Q.skip) {
+    HIP_TRY(Q.d_R.ensure((size_t)Q.l * sizeof(double)));
+    HIP_TRY(Q.d_heavy.ensure(std::max<size_t>(Q.heavy.size(), 1) * sizeof(int32_t)));
+    HIP_TRY(hipMemcpy(Q.d_R.p, Q.R.data(), (size_t)Q.l * sizeof(double), hipMemcpyHostToDevice));
+    if (!Q.heavy.empty())
+      HIP_TRY(hipMemcpy(Q.d_heavy.p, Q.heavy.data(), Q.heavy.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    Q.dev.skipR = Q.d_R.as<double>();
+    Q.dev.heavy = Q.d_heavy.as<int32_t>();
+  }
   return OI_OK;
 }
 
@@ -1550,6 +1587,8 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
     double* d_cdf = c.take<double>((size_t)Q.l + 1);
     oi::TabGroup* d_tab = c.take<oi::TabGroup>((size_t)ng);
     int32_t* d_shash = c.take<int32_t>(Q.shash.size());
+    double* d_R = Q.skip ? c.take<double>((size_t)Q.l) : nullptr;
+    int32_t* d_heavy = Q.skip ? c.take<int32_t>(Q.heavy.size()) : nullptr;
     unsigned long long* list1 = c.take<unsigned long long>(kNaLaunch);
     unsigned long long* list2 = c.take<unsigned long long>(kNaLaunch);
     // one block with an n-entry queue for samples that outgrow the main pool
@@ -1584,6 +1623,10 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
     qd.s0 = Q.S.size() == 1 ? Q.S[0] : -1;
     qd.qid = Q.qid;
     qd.beta0 = Q.beta0;
+    qd.skip = Q.skip ? 1 : 0;
+    qd.skipR = d_R;
+    qd.heavy = d_heavy;
+    qd.nheavy = (int64_t)Q.heavy.size();
     hipStream_t st = g->stream;
     oi_status status = OI_OK;
     // every exit below waits for the stream first: the copies read host
@@ -1593,6 +1636,12 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
       HIP_TRY(hipMemcpyAsync(d_cdf, Q.cdf.data(), (size_t)(Q.l + 1) * sizeof(double), hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(d_shash, Q.shash.data(), Q.shash.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
       HIP_TRY(hipMemcpyAsync(d_q, &qd, sizeof(qd), hipMemcpyHostToDevice, st));
+      if (Q.skip) {
+        HIP_TRY(hipMemcpyAsync(d_R, Q.R.data(), (size_t)Q.l * sizeof(double), hipMemcpyHostToDevice, st));
+        if (!Q.heavy.empty())
+          HIP_TRY(hipMemcpyAsync(d_heavy, Q.heavy.data(), Q.heavy.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                                 st));
+      }
       // the bitmaps must start empty (the array keeps whatever the last call left)
       HIP_TRY(oi::launch_clear_u64(reinterpret_cast<unsigned long long*>(gbits), (uint64_t)(words + 1) / 2, st));
       HIP_TRY(oi::launch_clear_u64(reinterpret_cast<unsigned long long*>(bits), ((uint64_t)blocks * words + 1) / 2,
@@ -1911,6 +1960,13 @@ oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap) {
     g->d_queue.release();
     g->large_blocks = 0;
   }
+  return OI_OK;
+}
+
+oi_status oi_set_stage1_skip(oi_graph* g, int64_t min_l) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (min_l < 1) return fail(OI_EINVAL, "min_l must be positive");
+  g->skip_min_l = min_l;
   return OI_OK;
 }
 

@@ -53,8 +53,18 @@ struct QueryDev {
   // no Stage 1, every node of S active from the start, Y = the nodes
   // outside S that end active (zero allowed); 0: IICP samples (Alg. 1)
   int32_t mc;
-  int32_t pad;
+  // 1: Stage 1 after the selection by skip sampling (long tables): entries
+  // with P >= 1/2 ("heavy", listed in `heavy`) by their own coins, the
+  // others by one walk per kSkipSeg-entry segment over `skipR`, the product
+  // of (1 - P_k) over the light entries of the segment up to each index
+  int32_t skip;
+  const double* skipR;   // l values (skip only)
+  const int32_t* heavy;  // nheavy table indices, ascending (skip only)
+  int64_t nheavy;
 };
+
+constexpr int64_t kSkipSeg = 256;       // entries per skip-sampling segment
+constexpr int64_t kSkipMinFloor = 65;   // shorter tables never use skip sampling
 
 // A contiguous range of samples of one query's stream.  Samples of all
 // segments of a launch are numbered by one flat index f; segment i covers
@@ -152,5 +162,6 @@ __host__ __device__ inline uint32_t mix32(uint32_t v) {
 constexpr int KIND_EDGE = 0;
 constexpr int KIND_SELECT = 1;
 constexpr int KIND_STAGE1 = 2;
+constexpr int KIND_SKIP = 3;
 
 }  // namespace oi
