@@ -17,6 +17,9 @@ query.
     python bench.py --workload cl4m [--queries Q] [--eps E] [--no-autotune]
         seed-set estimates/s, batched vs one at a time, on the 4M-node
         weighted-cascade graph, with the large-cascade kernel's roofline
+    python bench.py --workload accuracy [--queries Q]
+        relative errors of SOIEA, SIEA, MC_10K and MC_100K against a ground
+        truth (Sec. 6.1) on NetHEP- and NetPHY-sized synthetic graphs
     python bench.py --workload cl100m
         the 1e8-node / 1.5e9-edge graph: fixed-count throughput for
         |S| = 1, 10, 100, a SIEA estimate, the queue-cap comparison and the
@@ -391,6 +394,28 @@ def batched_vs_single_small(P, args):
             "rounds_per_estimate": sum(r["rounds"] for r in single) / q}
 
 
+def stage1_skip_gain(P, G, g, label, S, N, qid=0):
+    """Fixed-count IICP throughput of one long-table seed set with Stage-1 skip
+    sampling (the default for tables of >= 4096 entries) and with one coin per
+    table entry (skip sampling off): same law, different samples."""
+    import torch
+    out = {"workload": label, "k": int(len(S)), "samples": N}
+    for name, min_l in (("plain", 1 << 62), ("skip", 4096)):
+        P.oi_set_stage1_skip(G.h, min_l)
+        G.sample_fixed(S, N, query_id=qid)  # warm
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, _, r = G.sample_fixed(S, N, query_id=qid)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        out["l"] = r["l"]
+        out[name] = {"seconds": dt, "samples_per_s": N / dt, "mean_y": r["sum_y"] / N}
+    P.oi_set_stage1_skip(G.h, 4096)
+    out["speedup"] = out["plain"]["seconds"] / out["skip"]["seconds"]
+    log(f"stage-1 skip sampling, {label}: {out}")
+    return out
+
+
 def seed_spread(P, G, g, eps, delta, count):
     """One complete estimate for each of `count` seeded single-node seed sets
     (uniform over nodes with out-degree >= 1; the first is the headline's):
@@ -414,6 +439,37 @@ def seed_spread(P, G, g, eps, delta, count):
             "samples_per_s_max": float(v.max())}
 
 
+def accuracy_experiment(P, args):
+    """Sec. 6.1's accuracy comparison on stand-ins for NetHEP and NetPHY
+    (Chung-Lu graphs of their sizes) under the weighted-cascade and constant
+    edge models: average and maximum relative errors of SOIEA / SIEA at
+    eps = 0.1, delta = 1/n and of MC_10K / MC_100K against a ground truth
+    estimated at eps = 0.005, delta = 1/n, over `--queries` (default 1,000)
+    random single-node seed sets with out-degree >= 1, with each estimator's
+    GPU time."""
+    from oi_inputs.configs import ACCURACY_GRAPHS, ACCURACY_MODELS, accuracy_workload
+    from paper_1704_04794_amd.accuracy import accuracy
+    rows = []
+    for name in ACCURACY_GRAPHS:
+        for model in ACCURACY_MODELS:
+            g, sets = accuracy_workload(name, model, args.queries or 1000)
+            G = P.Graph.from_inputs(g)
+            G.estimate_batch(sets[:4], 0.5, 0.1)  # warm up kernels and workspaces
+            r = accuracy(G, sets)
+            G.close()
+            row = {"graph": name, "model": model, "n": g.n, "m": g.m, "sets": len(sets),
+                   "truth_seconds": r["truth"]["seconds"], "truth_samples": r["truth"]["samples"]}
+            for est in ("soiea", "siea", "mc_10000", "mc_100000"):
+                x = r[est]
+                row[est] = {f: round(x[f], 4) for f in ("avg_rel_err_oi", "max_rel_err_oi", "avg_rel_err_is",
+                                                         "max_rel_err_is", "seconds")}
+            rows.append(row)
+            log(f"accuracy {name} {model}: {row}")
+    return {"metric": "average / maximum relative error (%) of OI and IS estimates against a ground truth "
+                      "(eps = 0.005, delta = 1/n), as in the accuracy comparison of Sec. 6.1",
+            "data": "synthetic stand-ins (Chung-Lu, gamma 2.1) of NetHEP and NetPHY sizes", "rows": rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,7 +481,7 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--pipeline", type=int, choices=(0, 1, 2), default=None,
                     help="RSA rounds: 0 read back one at a time, 1 queued (default), 2 queued, one graph each")
-    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m", "er2k"), default="cl1m",
+    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m", "er2k", "accuracy"), default="cl1m",
                     help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time; "
                          "cl100m: the billion-edge graph; er2k: batched vs one-at-a-time where one query "
                          "leaves the GPU idle")
@@ -471,6 +527,9 @@ def main():
         return
     if args.workload == "cl100m":
         print(json.dumps(billion_edge(P, args)), flush=True)
+        return
+    if args.workload == "accuracy":
+        print(json.dumps(accuracy_experiment(P, args)), flush=True)
         return
     t = time.perf_counter()
     g, sets, extra = make_config("cl1m")
@@ -538,6 +597,10 @@ def main():
                                        "handed_large", "tiny_y", "small_y", "large_y")},
     }
     out["spread"] = seed_spread(P, G, g, eps, delta, args.spread)
+    from oi_inputs import top_outdeg_seed_set
+    out["stage1_skip"] = stage1_skip_gain(
+        P, G, g, "cl1m (trivalency p), 1,000 seeds from the top-1% out-degree nodes",
+        top_outdeg_seed_set(g, 1000, 7), 1 << 18, qid=99)
     gr = gather_roofline(G)
     out["roofline"]["measured_gather_gbps"] = gr["gbps"]
     out["roofline"]["frac_of_measured_gather"] = achieved / gr["gbps"] if gr["gbps"] > 0 else None

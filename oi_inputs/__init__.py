@@ -20,9 +20,11 @@ from .graphs import (  # noqa: F401
     trivalency_probs,
     sigmoid_theta_probs,
     uniform_probs,
+    constant_probs,
     seed_node_outdeg_ge1,
+    outdeg_ge1_nodes,
     uniform_seed_set,
     top_outdeg_seed_set,
     batched_seed_sets,
 )
-from .configs import CONFIGS, make_config  # noqa: F401
+from .configs import ACCURACY_GRAPHS, CONFIGS, accuracy_workload, make_config  # noqa: F401

@@ -87,3 +87,27 @@ def make_config(name: str, n: int | None = None, m: int | None = None, progress=
     else:
         raise ValueError(name)
     return g, sets, extra
+
+
+# Stand-ins for the two smallest networks of the accuracy experiment (Sec. 6,
+# Table 2: NetHEP about 15K nodes / 59K edges, NetPHY about 37K / 181K):
+# Chung-Lu graphs of those sizes, under the weighted-cascade model and the
+# constant models p = 0.1, 0.01, 0.001 of Sec. 6.1.
+ACCURACY_GRAPHS = {"hep15k": dict(n=15_000, m=59_000, seed=31), "phy37k": dict(n=37_000, m=181_000, seed=32)}
+ACCURACY_MODELS = ("wc", "p0.1", "p0.01", "p0.001")
+
+
+def accuracy_workload(name: str, model: str, sets: int = 1000):
+    """(graph, seed sets) of the accuracy experiment: `sets` distinct single
+    nodes with out-degree >= 1 (seed 300 + the graph's seed)."""
+    c = ACCURACY_GRAPHS[name]
+    g = G.chung_lu_graph(c["n"], c["m"], 2.1, c["seed"])
+    if model == "wc":
+        p = G.wc_probs(g)
+    elif model.startswith("p"):
+        p = G.constant_probs(g, float(model[1:]))
+    else:
+        raise ValueError(model)
+    g = g.with_p(p)
+    nodes = G.outdeg_ge1_nodes(g, sets, 300 + c["seed"])
+    return g, [np.array([v], np.int32) for v in nodes]

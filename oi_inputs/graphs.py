@@ -267,6 +267,11 @@ def sigmoid_theta_probs(g: Graph, seed: int, mu: float = -3.0, sd: float = 1.0):
     return theta, p
 
 
+def constant_probs(g: Graph, p: float) -> np.ndarray:
+    """The constant edge model of Sec. 6: every edge has probability p."""
+    return np.full(g.m, p, dtype=np.float32)
+
+
 def uniform_probs(g: Graph, seed: int, lo: float, hi: float) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     return rng.uniform(lo, hi, size=g.m).astype(np.float32)
@@ -281,6 +286,14 @@ def seed_node_outdeg_ge1(g: Graph, seed: int) -> np.ndarray:
     rng = np.random.Generator(np.random.PCG64(seed))
     cand = np.flatnonzero(g.outdeg() >= 1)
     return np.array([cand[rng.integers(0, cand.size)]], dtype=np.int32)
+
+
+def outdeg_ge1_nodes(g: Graph, count: int, seed: int) -> np.ndarray:
+    """`count` distinct nodes drawn uniformly among nodes with out-degree >= 1
+    (single-node seed sets whose outward influence is positive)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cand = np.flatnonzero(g.outdeg() >= 1)
+    return np.sort(rng.choice(cand, size=min(count, cand.size), replace=False)).astype(np.int32)
 
 
 def uniform_seed_set(g: Graph, k: int, seed: int) -> np.ndarray:
