@@ -58,6 +58,8 @@ def lib():
         L.oo_sample_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, vp, C.c_int]
         L.oo_stage1.argtypes = g + [vp, i64, i64, _P(i64), _P(dbl), vp, vp, vp, vp, _P(i64)]
         L.oo_mc_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, _P(i64), C.c_int]
+        L.oo_lt_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, _P(i64), C.c_int]
+        L.oo_estimate_lt.argtypes = g + [vp, i64, dbl, dbl, u32, u32, _P(dbl), _P(dbl), _P(i64), _P(RsaResult)]
         L.oo_selection.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp]
         L.oo_rsa_arrays.argtypes = [vp, u64, vp, u64, dbl, dbl, dbl, dbl, dbl, dbl, _P(RsaResult)]
         L.oo_gsra_array.argtypes = [vp, u64, dbl, dbl, dbl, dbl, dbl, dbl, _P(dbl), _P(u64), _P(u64), _P(dbl)]
@@ -66,7 +68,7 @@ def lib():
                                       _P(i64), _P(RsaResult)]
         L.oo_exact.argtypes = g + [vp, i64, _P(dbl), vp, vp]
         L.oo_backward.argtypes = g + [vp, i64, u32, u32, u64, u64, vp, vp, _P(u64), _P(dbl), C.c_int]
-        for f in ("oo_sample_fixed", "oo_mc_fixed", "oo_stage1", "oo_selection", "oo_rsa_arrays", "oo_gsra_array", "oo_rsa_plan",
+        for f in ("oo_sample_fixed", "oo_mc_fixed", "oo_lt_fixed", "oo_estimate_lt", "oo_stage1", "oo_selection", "oo_rsa_arrays", "oo_gsra_array", "oo_rsa_plan",
                   "oo_estimate", "oo_exact", "oo_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
@@ -193,6 +195,39 @@ def mc_fixed(g, seeds, qid: int, seed: int, stream: int, first: int, count: int,
     k = kk.value
     oi = int(sums[0]) / count if count else 0.0
     return dict(y=y, e=e, sum_y=int(sums[0]), sum_e=int(sums[1]), k=k, oi=oi, is_=k + oi)
+
+
+def lt_fixed(g, seeds, qid: int, seed: int, stream: int, first: int, count: int,
+             want_y: bool = True, want_e: bool = False, nthreads: int | None = None):
+    """LT-model cascades (reading R17): per-sample Y = |cascade| - |S| and E of
+    samples first..first+count-1.  Returns dict(y, e, sum_y, sum_e, k, is_, oi)
+    with the fixed-count estimates is_ = |S| + mean(Y), oi = mean(Y)."""
+    gg = _graph(g)
+    s = _seeds(seeds)
+    y = np.zeros(count, np.uint32) if want_y else None
+    e = np.zeros(count, np.uint64) if want_e else None
+    sums = np.zeros(2, np.uint64)
+    kk = C.c_int64()
+    nt = nthreads_default() if nthreads is None else nthreads
+    rc = lib().oo_lt_fixed(*_gargs(gg), _ptr(s), s.size, qid, seed, stream, first, count,
+                           _ptr(y), _ptr(e), _ptr(sums), C.byref(kk), nt)
+    _chk("lt_fixed", rc)
+    k = kk.value
+    oi = int(sums[0]) / count if count else 0.0
+    return dict(y=y, e=e, sum_y=int(sums[0]), sum_e=int(sums[1]), k=k, oi=oi, is_=k + oi)
+
+
+def estimate_lt(g, seeds, eps, delta, qid: int, seed: int):
+    """SIEA_LT: RSA on LT cascade sizes.  Returns dict(oi, is_, k, rsa)."""
+    gg = _graph(g)
+    s = _seeds(seeds)
+    oi, is_ = C.c_double(), C.c_double()
+    kk = C.c_int64()
+    r = RsaResult()
+    rc = lib().oo_estimate_lt(*_gargs(gg), _ptr(s), s.size, eps, delta, qid, seed, C.byref(oi), C.byref(is_),
+                              C.byref(kk), C.byref(r))
+    _chk("estimate_lt", rc)
+    return dict(oi=oi.value, is_=is_.value, k=kk.value, rsa=r.as_dict())
 
 
 def selection(g, seeds, qid: int, seed: int, stream: int, first: int, count: int):

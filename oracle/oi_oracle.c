@@ -57,6 +57,17 @@
  *       sum of squared differences of Y'.
  *   R12 beta_0 = 0 (S has no out-neighbour outside S): OI = 0, IS = |S|, no
  *       samples are drawn.
+ *   R17 The LT model (Sec. 5.3, and SIEA_LT in the experiments) in its
+ *       live-edge form (Kempe et al.): every node v keeps at most one of its
+ *       in-edges, edge (u, v) with probability w(u, v) and none with
+ *       probability 1 - sum_u w(u, v) (which must be >= 0; sums up to
+ *       1 + 1e-6 are taken as 1).  v's choice is the word W_v = word (v mod 4)
+ *       of the Philox block kind 4, idx = v div 4; v's in-edges, in ascending
+ *       edge id, own consecutive intervals [t_{k-1}, t_k) of the 2^32 words,
+ *       t_k = floor(min(c_k, 1) * 2^32) with c_k the fp64 running sum of their
+ *       weights (left to right), and an edge is live iff W_v falls in its
+ *       interval.  An LT sample is the set reachable from S over live edges;
+ *       SIEA_LT runs RSA on its size X = |S| + Y over [a, b] = [|S|, n].
  *   R16 Stage-1 skip sampling (a different consumption of randomness for the
  *       same law, used when l >= max(skip_min_l, 65); skip_min_l = 4096 unless
  *       set): after the selection i, entries with P_j >= 1/2 ("heavy") are
@@ -83,7 +94,7 @@
 typedef unsigned __int128 oo_u128;
 
 enum { OO_OK = 0, OO_EINVAL = -1, OO_ERANGE = -2, OO_ENOMEM = -3 };
-enum { KIND_EDGE = 0, KIND_SELECT = 1, KIND_STAGE1 = 2, KIND_SKIP = 3 };
+enum { KIND_EDGE = 0, KIND_SELECT = 1, KIND_STAGE1 = 2, KIND_SKIP = 3, KIND_LT = 4 };
 
 /* R16: the spec's constants and the table size from which skip sampling is used */
 enum { SKIP_SEG = 256, SKIP_LMIN_FLOOR = 65 };
@@ -623,6 +634,151 @@ int oo_mc_fixed(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col
     return rc;
 }
 
+/* ------------------------------------------------------------------------ */
+/* LT model cascades (R17)                                                   */
+/* ------------------------------------------------------------------------ */
+/* Per-edge selection intervals [lo[e], hi[e]) of the 2^32 words (R17). */
+static int lt_intervals(const oo_graph *g, uint64_t *lo, uint64_t *hi)
+{
+    int64_t n = g->n, m = g->m;
+    int64_t *cnt = calloc((size_t)n + 1, sizeof(int64_t));
+    int64_t *ord = malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+    if (!cnt || !ord) { free(cnt); free(ord); return OO_ENOMEM; }
+    for (int64_t e = 0; e < m; ++e) cnt[g->col[e] + 1]++;
+    for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+    int64_t *pos = malloc(sizeof(int64_t) * (size_t)(n ? n : 1));
+    if (!pos) { free(cnt); free(ord); return OO_ENOMEM; }
+    for (int64_t v = 0; v < n; ++v) pos[v] = cnt[v];
+    for (int64_t e = 0; e < m; ++e) ord[pos[g->col[e]]++] = e;   /* ascending e per target */
+    int rc = OO_OK;
+    for (int64_t v = 0; v < n && rc == OO_OK; ++v) {
+        double c = 0.0;
+        uint64_t prev = 0;
+        for (int64_t q = cnt[v]; q < cnt[v + 1]; ++q) {
+            int64_t e = ord[q];
+            c = c + (double)g->p[e];
+            if (c > 1.0 + 1e-6) { rc = OO_EINVAL; break; }
+            uint64_t t = (uint64_t)((c < 1.0 ? c : 1.0) * 4294967296.0);
+            lo[e] = prev;
+            hi[e] = t;
+            prev = t;
+        }
+    }
+    free(cnt); free(ord); free(pos);
+    return rc;
+}
+
+static uint32_t lt_word(uint32_t qid, uint32_t seed, uint32_t stream, uint64_t s, int32_t v)
+{
+    uint32_t r[4];
+    draw(qid, seed, KIND_LT, stream, s, (uint64_t)v >> 2, r);
+    return r[v & 3];
+}
+
+/* One LT cascade from S (R17): returns Y, the nodes outside S reached;
+ * *E_out = out-degree summed over the nodes expanded, S included. */
+static uint32_t lt_sample(const oo_graph *g, const oo_table *t, const uint64_t *lo, const uint64_t *hi,
+                          uint32_t qid, uint32_t seed, uint32_t stream, uint64_t s, uint64_t *E_out,
+                          oo_scratch *w)
+{
+    int64_t head = 0, tail = 0;
+    uint64_t E = 0;
+    for (int64_t i = 0; i < t->k; ++i) {
+        w->queue[tail++] = t->S[i];
+        w->vis[t->S[i]] = 1;
+    }
+    while (head < tail) {
+        int32_t u = w->queue[head++];
+        int64_t b = g->row_ptr[u], e1 = g->row_ptr[u + 1];
+        E += (uint64_t)(e1 - b);
+        for (int64_t e = b; e < e1; ++e) {
+            int32_t v = g->col[e];
+            if (w->vis[v]) continue;
+            uint64_t W = lt_word(qid, seed, stream, s, v);
+            if (lo[e] <= W && W < hi[e]) {
+                w->vis[v] = 1;
+                w->queue[tail++] = v;
+            }
+        }
+    }
+    for (int64_t h = 0; h < tail; ++h) w->vis[w->queue[h]] = 0;
+    if (E_out) *E_out = E;
+    return (uint32_t)(tail - t->k);
+}
+
+typedef struct {
+    const oo_graph *g; const oo_table *t; const uint64_t *lo, *hi;
+    uint32_t qid, seed, stream;
+    uint64_t first, count;
+    uint32_t *y_out; uint64_t *e_out;
+    uint64_t sumY, sumE;
+    int rc;
+} lt_job;
+
+static void *lt_worker(void *arg)
+{
+    lt_job *j = arg;
+    oo_scratch w;
+    if (scratch_init(&w, j->g->n)) { j->rc = OO_ENOMEM; return NULL; }
+    uint64_t sy = 0, se = 0;
+    for (uint64_t q = 0; q < j->count; ++q) {
+        uint64_t E;
+        uint32_t Y = lt_sample(j->g, j->t, j->lo, j->hi, j->qid, j->seed, j->stream, j->first + q, &E, &w);
+        if (j->y_out) j->y_out[q] = Y;
+        if (j->e_out) j->e_out[q] = E;
+        sy += Y;
+        se += E;
+    }
+    scratch_free(&w);
+    j->sumY = sy;
+    j->sumE = se;
+    j->rc = OO_OK;
+    return NULL;
+}
+
+/* Oracle entry: `count` LT cascades (R17) of stream `stream` from index
+ * `first`: per-sample Y = |cascade| - |S| and E; sums = [sum Y, sum E]. */
+int oo_lt_fixed(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                const float *p, const int32_t *seeds, int64_t k, uint32_t qid,
+                uint32_t seed, uint32_t stream, uint64_t first, uint64_t count,
+                uint32_t *y_out, uint64_t *e_out, uint64_t *sums, int64_t *k_out, int nthreads)
+{
+    oo_graph g = {n, m, row_ptr, col, p};
+    oo_table t;
+    int rc = oo_table_build(&g, seeds, k, &t);
+    if (rc) return rc;
+    if (k_out) *k_out = t.k;
+    sums[0] = sums[1] = 0;
+    uint64_t *lo = malloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+    uint64_t *hi = malloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+    if (!lo || !hi) { free(lo); free(hi); oo_table_free(&t); return OO_ENOMEM; }
+    rc = lt_intervals(&g, lo, hi);
+    if (rc || count == 0) { free(lo); free(hi); oo_table_free(&t); return rc; }
+    if (nthreads < 1) nthreads = 1;
+    if ((uint64_t)nthreads > count) nthreads = (int)count;
+    lt_job *jobs = calloc((size_t)nthreads, sizeof(lt_job));
+    pthread_t *th = calloc((size_t)nthreads, sizeof(pthread_t));
+    uint64_t per = count / (uint64_t)nthreads, rem = count % (uint64_t)nthreads, off = 0;
+    for (int i = 0; i < nthreads; ++i) {
+        uint64_t c = per + ((uint64_t)i < rem ? 1 : 0);
+        jobs[i] = (lt_job){&g, &t, lo, hi, qid, seed, stream, first + off, c,
+                           y_out ? y_out + off : NULL, e_out ? e_out + off : NULL, 0, 0, 0};
+        off += c;
+        if (nthreads == 1) lt_worker(&jobs[i]);
+        else pthread_create(&th[i], NULL, lt_worker, &jobs[i]);
+    }
+    rc = OO_OK;
+    for (int i = 0; i < nthreads; ++i) {
+        if (nthreads > 1) pthread_join(th[i], NULL);
+        if (jobs[i].rc) rc = jobs[i].rc;
+        sums[0] += jobs[i].sumY;
+        sums[1] += jobs[i].sumE;
+    }
+    free(jobs); free(th); free(lo); free(hi);
+    oo_table_free(&t);
+    return rc;
+}
+
 /* Stage-1 table export for tests: copies l entries into caller arrays (any may
  * be NULL), returns l through *l_out and beta_0 through *beta0. */
 int oo_stage1(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const float *p,
@@ -916,6 +1072,51 @@ int oo_estimate(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col
         if (mode == 0) { *oi = t.beta0 * r->mu; *is = *oi + kd; }   /* Alg. 4's output */
         else { *is = r->mu; *oi = *is - kd; }                        /* Alg. 5's output */
     }
+    oo_table_free(&t);
+    return rc;
+}
+
+/* SIEA_LT (R17): RSA (Alg. 3) on X = |S| + Y with Y from LT cascades,
+ * [a, b] = [|S|, n].  IS = the RSA estimate, OI = IS - |S|. */
+typedef struct {
+    const oo_graph *g; const oo_table *t; const uint64_t *lo, *hi; uint32_t qid, seed; oo_scratch w;
+} lt_ctx;
+
+static uint32_t lt_next(void *c, uint32_t stream, uint64_t index)
+{
+    lt_ctx *x = c;
+    return lt_sample(x->g, x->t, x->lo, x->hi, x->qid, x->seed, stream, index, NULL, &x->w);
+}
+
+int oo_estimate_lt(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, const float *p,
+                   const int32_t *seeds, int64_t k, double eps, double delta, uint32_t qid, uint32_t seed,
+                   double *oi, double *is, int64_t *k_out, oo_rsa_result *r)
+{
+    oo_graph g = {n, m, row_ptr, col, p};
+    oo_table t;
+    memset(r, 0, sizeof(*r));
+    if (!(eps > 0.0 && eps < 1.0) || !(delta > 0.0 && delta < 0.5)) return OO_EINVAL;
+    int rc = oo_table_build(&g, seeds, k, &t);
+    if (rc) return rc;
+    *k_out = t.k;
+    double kd = (double)t.k;
+    if (t.beta0 == 0.0 || t.k >= n) {   /* no edge leaves S: the cascade is S */
+        *oi = 0.0; *is = kd;
+        oo_table_free(&t);
+        return OO_OK;
+    }
+    uint64_t *lo = malloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+    uint64_t *hi = malloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+    if (!lo || !hi) { free(lo); free(hi); oo_table_free(&t); return OO_ENOMEM; }
+    rc = lt_intervals(&g, lo, hi);
+    if (rc) { free(lo); free(hi); oo_table_free(&t); return rc; }
+    lt_ctx c;
+    c.g = &g; c.t = &t; c.lo = lo; c.hi = hi; c.qid = qid; c.seed = seed;
+    if (scratch_init(&c.w, n)) { free(lo); free(hi); oo_table_free(&t); return OO_ENOMEM; }
+    rc = oo_rsa(lt_next, &c, eps, delta, kd, (double)n, 1.0, kd, r);
+    scratch_free(&c.w);
+    free(lo); free(hi);
+    if (rc == OO_OK) { *is = r->mu; *oi = *is - kd; }
     oo_table_free(&t);
     return rc;
 }
