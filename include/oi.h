@@ -49,8 +49,11 @@ typedef enum {
 } oi_status;
 
 /* SOIEA estimates OI(S) with X = Y (Alg. 4); SIEA estimates IS(S) with
- * X = Z = beta_0 * Y + |S| (Eq. z_s, Alg. 5).  Both report OI and IS. */
-typedef enum { OI_MODE_SOIEA = 0, OI_MODE_SIEA = 1 } oi_mode;
+ * X = Z = beta_0 * Y + |S| (Eq. z_s, Alg. 5).  SIEA_LT (Sec. 5.3 and the LT
+ * experiment of Sec. 6) estimates IS(S) under the LT model: RSA on the
+ * sizes X = |S| + Y of LT cascades (oi_sample_lt) over [|S|, n], the edge
+ * probabilities being the LT weights.  All report OI and IS = OI + |S|. */
+typedef enum { OI_MODE_SOIEA = 0, OI_MODE_SIEA = 1, OI_MODE_SIEA_LT = 2 } oi_mode;
 
 /* Gradient with respect to p_e, or to theta_e where p_e = sigmoid(theta_e). */
 typedef enum { OI_PARAM_P = 0, OI_PARAM_THETA = 1 } oi_param;
@@ -147,6 +150,25 @@ oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, 
  * Samples are drawn even when beta_0 = 0 (they are then all zero).
  */
 oi_status oi_sample_mc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
+                       uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums);
+
+/*
+ * LT-model cascades (the model of Kempe et al. that Sec. 5.3 and the LT
+ * experiment of Sec. 6 use with SIEA_LT), samples first .. first+count-1
+ * of stream `stream`, the edge probabilities read as LT weights w(u, v) (the
+ * in-weights of every node must sum to at most 1; up to 1e-6 of rounding
+ * is taken as 1, more gives OI_EINVAL).  Live-edge form: every node v keeps
+ * at most one in-edge, (u, v) with probability w(u, v); its choice is the
+ * word W_v = word (v mod 4) of the Philox block kind 4, idx v div 4, and its
+ * in-edges in ascending edge id own consecutive intervals [t_{k-1}, t_k),
+ * t_k = floor(min(c_k, 1) * 2^32), c_k the fp64 running sum of their
+ * weights; edge (u, v) is live iff W_v lies in its interval.  A sample is
+ * the set reachable from S over live edges.  y_out, e_out and sums as in
+ * oi_sample_mc (Y = |cascade| - |S|; is = |S| + mean(Y), oi = mean(Y)).
+ * The per-edge intervals (8 bytes per edge) are made on the first LT call
+ * and kept until the probabilities change.
+ */
+oi_status oi_sample_lt(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
                        uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums);
 
 /*

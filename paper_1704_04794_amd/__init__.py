@@ -9,11 +9,11 @@ from __future__ import annotations
 import numpy as np
 
 from ._binding import (  # noqa: F401
-    LIB_PATH, OI_MODE_SIEA, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_autotune, oi_backward,
+    LIB_PATH, OI_MODE_SIEA, OI_MODE_SIEA_LT, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_autotune, oi_backward,
     oi_gather_probe,
     oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
     oi_graph_set_theta, oi_last_error,
-    oi_num_variants, oi_sample_fixed, oi_sample_fixed_noalloc, oi_sample_mc, oi_set_pipeline, oi_set_routing, oi_set_stage1_skip, oi_set_stream, oi_set_tuning, oi_stage1_table,
+    oi_num_variants, oi_sample_fixed, oi_sample_fixed_noalloc, oi_sample_lt, oi_sample_mc, oi_set_pipeline, oi_set_routing, oi_set_stage1_skip, oi_set_stream, oi_set_tuning, oi_stage1_table,
     oi_timing_enable, oi_timing_get, oi_variant_info)
 
 RUN_SEED = 0x17044794
@@ -96,6 +96,17 @@ class Graph:
         y = torch.empty(count, dtype=torch.int32, device=device)
         e = torch.empty(count, dtype=torch.int64, device=device) if want_e else None
         r = oi_sample_mc(self.h, query_id, seeds, stream, first, count, run_seed, y, e)
+        return y, e, r
+
+    def sample_lt(self, seeds, count, first=0, stream=0, query_id=0, run_seed=RUN_SEED, want_e=False,
+                  device="cuda"):
+        """LT-model cascades (edge probabilities as LT weights): Y = |cascade|
+        - |S| (and optionally E) of `count` samples as torch tensors, with the
+        fixed-count estimates."""
+        import torch
+        y = torch.empty(count, dtype=torch.int32, device=device)
+        e = torch.empty(count, dtype=torch.int64, device=device) if want_e else None
+        r = oi_sample_lt(self.h, query_id, seeds, stream, first, count, run_seed, y, e)
         return y, e, r
 
     def estimate(self, seeds, eps, delta, mode=OI_MODE_SOIEA, query_id=0, run_seed=RUN_SEED):

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboi_hip.so")
 
 OI_OK, OI_EINVAL, OI_ERANGE, OI_ENOMEM, OI_EHIP, OI_ESTATE = 0, -1, -2, -3, -4, -5
-OI_MODE_SOIEA, OI_MODE_SIEA = 0, 1
+OI_MODE_SOIEA, OI_MODE_SIEA, OI_MODE_SIEA_LT = 0, 1, 2
 OI_PARAM_P, OI_PARAM_THETA = 0, 1
 
 
@@ -86,6 +86,7 @@ def _load():
         "oi_sample_fixed": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
         "oi_sample_fixed_noalloc": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
         "oi_sample_mc": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
+        "oi_sample_lt": [vp, u32, vp, i64, ci, u64, u64, u32, vp, vp, P(oi_result)],
         "oi_estimate": [vp, u32, vp, i64, dbl, dbl, ci, u32, P(oi_result)],
         "oi_estimate_batch": [vp, i32, vp, vp, vp, dbl, dbl, ci, u32, vp],
         "oi_backward": [vp, u32, vp, i64, u64, u64, u32, vp, ci, dbl, vp],
@@ -216,6 +217,14 @@ def oi_sample_mc(g, query_id, seeds, stream, first, count, run_seed, y_out=None,
     s = _host(seeds, np.int32)
     r = oi_result()
     _check("oi_sample_mc", _lib.oi_sample_mc(g, int(query_id), _ptr(s), s.size, int(stream), int(first),
+                                              int(count), int(run_seed), _ptr(y_out), _ptr(e_out), C.byref(r)))
+    return r.as_dict()
+
+
+def oi_sample_lt(g, query_id, seeds, stream, first, count, run_seed, y_out=None, e_out=None):
+    s = _host(seeds, np.int32)
+    r = oi_result()
+    _check("oi_sample_lt", _lib.oi_sample_lt(g, int(query_id), _ptr(s), s.size, int(stream), int(first),
                                               int(count), int(run_seed), _ptr(y_out), _ptr(e_out), C.byref(r)))
     return r.as_dict()
 

@@ -31,13 +31,15 @@ def _rel_err(est, truth):
 
 
 def accuracy(G, seed_sets, eps=0.1, delta=None, truth_eps=0.005, truth_delta=None, mc_samples=(10_000, 100_000),
-             run_seed=RUN_SEED, truth_seed=TRUTH_SEED, query_ids=None):
+             run_seed=RUN_SEED, truth_seed=TRUTH_SEED, query_ids=None, truth_chunk=None, progress=None):
     """Run the experiment on graph G (a paper_1704_04794_amd.Graph) for the
     given seed sets (every set needs an out-neighbour outside itself, so that
     its outward influence is positive).  Returns a dict with, per estimator
     ("soiea", "siea", "mc_<N>"), the per-set estimates of OI and IS, the
     average and maximum relative errors (%) of both, and the wall time of the
-    estimator's calls; plus the ground truth and its time."""
+    estimator's calls; plus the ground truth and its time.  The ground truth
+    is estimated in batched calls of `truth_chunk` sets (default: all at
+    once), calling progress(done, total) after each."""
     import torch
     n = G.n
     delta = 1.0 / n if delta is None else delta
@@ -47,7 +49,13 @@ def accuracy(G, seed_sets, eps=0.1, delta=None, truth_eps=0.005, truth_delta=Non
     out = {"sets": len(seed_sets), "eps": eps, "delta": delta, "truth_eps": truth_eps, "truth_delta": truth_delta}
 
     t = time.perf_counter()
-    tr = G.estimate_batch(seed_sets, truth_eps, truth_delta, mode=OI_MODE_SOIEA, query_ids=q, run_seed=truth_seed)
+    tr = []
+    step = truth_chunk or len(seed_sets)
+    for lo in range(0, len(seed_sets), step):
+        tr += G.estimate_batch(seed_sets[lo:lo + step], truth_eps, truth_delta, mode=OI_MODE_SOIEA,
+                               query_ids=q[lo:lo + step], run_seed=truth_seed)
+        if progress:
+            progress(len(tr), len(seed_sets))
     out["truth"] = {"seconds": time.perf_counter() - t,
                     "oi": [r["oi"] for r in tr], "is": [r["is_"] for r in tr],
                     "samples": int(sum(r["samples_x"] + r["samples_xp"] for r in tr))}

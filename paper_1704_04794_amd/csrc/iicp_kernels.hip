@@ -851,9 +851,10 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
             A.list2[pos] = f;
             start = false;
           }
-        } else if (mc ? Q.k != 1 : Q.skip != 0) {
-          // a Monte-Carlo sample from several seeds (the large kernel queues
-          // the whole seed set), or a long table's skip-sampled Stage 1
+        } else if (Q.lt || (mc ? Q.k != 1 : Q.skip != 0)) {
+          // an LT cascade, a Monte-Carlo sample from several seeds (the large
+          // kernel queues the whole seed set), or a long table's skip-sampled
+          // Stage 1
           const unsigned int pos = atomicAdd(A.nlist2, 1u);
           A.list2[pos] = f;
           start = false;
@@ -1247,7 +1248,8 @@ __device__ __forceinline__ void push(int32_t* queue, uint32_t* tail, uint32_t qc
   if (pos < qcap) queue[pos] = v;
 }
 
-template <bool BWD, int NT>
+// LT: the launch's samples are LT-model cascades (forward only).
+template <bool BWD, int NT, bool LT>
 __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_tail;
   __shared__ unsigned long long s_E;
@@ -1484,14 +1486,27 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
           va[u] = *(const OI_GLOBAL v4i32*)q;
           pa[u] = *(const OI_GLOBAL v4i32*)(q + 16);
         }
+        if (!LT) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) d[u] = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, gg[u]);
+          for (int u = 0; u < 2; ++u) d[u] = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, gg[u]);
+        }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const uint32_t e = 4 * gg[u] + b;
-            if (e >= lo_e[u] && e < hi_e[u]) {
+            if (LT && e >= lo_e[u] && e < hi_e[u]) {
+              // the LT model: v activates through e iff v's choice word
+              // falls in e's interval (S is marked, so an edge into S and a
+              // node already active draw nothing)
+              const int32_t v = va[u][b];
+              if (!((gptr(bits)[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u)) {
+                const Words dv = philox_draw(Q.qid, A.seed, KIND_LT, S.stream, s, (uint64_t)((uint32_t)v >> 2));
+                const uint32_t W = word_at(dv, v & 3);
+                const OI_GLOBAL LtEdge* iv = gptr(A.lt_iv) + e;
+                if (W >= iv->lo && W <= iv->last && claim(bits, v)) push(queue, &s_tail, A.qcap, v);
+              }
+            } else if (!LT && e >= lo_e[u] && e < hi_e[u]) {
               const bool live = edge_live(d[u].w[b], (uint32_t)pa[u][b]);
               const int32_t v = va[u][b];
               if (BWD) {
@@ -1984,26 +1999,37 @@ hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t 
 }
 
 hipError_t large_occupancy(bool bwd, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu,
-      bwd ? reinterpret_cast<const void*>(&large_kernel<true, LB>)
-          : reinterpret_cast<const void*>(&large_kernel<false, LB>),
+  // the pool is sized for the most demanding instantiation of the main pool
+  int a = 0, b = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &a,
+      bwd ? reinterpret_cast<const void*>(&large_kernel<true, LB, false>)
+          : reinterpret_cast<const void*>(&large_kernel<false, LB, false>),
       LB, 0);
+  if (e == hipSuccess && !bwd)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, reinterpret_cast<const void*>(&large_kernel<false, LB, true>),
+                                                     LB, 0);
+  *blocks_per_cu = bwd ? a : (a > b ? a : b);
+  return e;
 }
 
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
   if (bwd)
-    hipLaunchKernelGGL((large_kernel<true, LB>), dim3(blocks), dim3(LB), 0, st, A);
+    hipLaunchKernelGGL((large_kernel<true, LB, false>), dim3(blocks), dim3(LB), 0, st, A);
+  else if (A.lt)
+    hipLaunchKernelGGL((large_kernel<false, LB, true>), dim3(blocks), dim3(LB), 0, st, A);
   else
-    hipLaunchKernelGGL((large_kernel<false, LB>), dim3(blocks), dim3(LB), 0, st, A);
+    hipLaunchKernelGGL((large_kernel<false, LB, false>), dim3(blocks), dim3(LB), 0, st, A);
   return hipGetLastError();
 }
 
 hipError_t launch_large_full(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
   if (bwd)
-    hipLaunchKernelGGL((large_kernel<true, LB_FULL>), dim3(blocks), dim3(LB_FULL), 0, st, A);
+    hipLaunchKernelGGL((large_kernel<true, LB_FULL, false>), dim3(blocks), dim3(LB_FULL), 0, st, A);
+  else if (A.lt)
+    hipLaunchKernelGGL((large_kernel<false, LB_FULL, true>), dim3(blocks), dim3(LB_FULL), 0, st, A);
   else
-    hipLaunchKernelGGL((large_kernel<false, LB_FULL>), dim3(blocks), dim3(LB_FULL), 0, st, A);
+    hipLaunchKernelGGL((large_kernel<false, LB_FULL, false>), dim3(blocks), dim3(LB_FULL), 0, st, A);
   return hipGetLastError();
 }
 

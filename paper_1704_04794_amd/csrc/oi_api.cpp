@@ -195,6 +195,9 @@ struct oi_graph {
   // valid while d_p_ok
   DevBuf d_p;
   bool d_p_ok = false;
+  // LT-model intervals per edge, made on the first LT call, valid while d_lt_ok
+  DevBuf d_lt;
+  bool d_lt_ok = false;
   // per-launch workspaces
   DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_bits, d_queue;
   // backward workspaces, kept between calls (the per-edge and per-node sums
@@ -551,7 +554,10 @@ oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t
   const uint64_t want_waves = (A.total + 63) / 64;
   int bpc = 0;
   if (ev) HIP_TRY(hipEventRecord(ev[0], st));
-  if (g->use_tiny) {
+  // LT cascades start in the small kernel (which hands them all on)
+  const bool tiny = g->use_tiny && !A.lt;
+  A.small_from_list1 = tiny ? 1 : 0;
+  if (tiny) {
     HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
     if (bpc < 1) bpc = 1;
     const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
@@ -603,6 +609,48 @@ oi_status elapsed(hipEvent_t a, hipEvent_t b, float* ms) {
   return OI_OK;
 }
 
+// The LT model's per-edge intervals (live-edge form): the in-edges of each
+// node v, in ascending edge id, own consecutive ranges [t_{k-1}, t_k) of
+// v's 32-bit choice word, t_k = floor(min(c_k, 1) * 2^32) with c_k the fp64
+// running sum of their weights; in-weights must sum to at most 1 (up to
+// 1e-6 of rounding).
+oi_status ensure_lt(oi_graph* g) {
+  if (g->d_lt_ok) return OI_OK;
+  const int64_t n = g->n, m = g->m;
+  std::vector<int64_t> cnt((size_t)n + 1, 0), pos((size_t)n, 0), ord((size_t)std::max<int64_t>(m, 1));
+  for (int64_t e = 0; e < m; ++e) cnt[(size_t)g->col[e] + 1]++;
+  for (int64_t v = 0; v < n; ++v) cnt[v + 1] += cnt[v];
+  for (int64_t v = 0; v < n; ++v) pos[v] = cnt[v];
+  for (int64_t e = 0; e < m; ++e) ord[(size_t)pos[g->col[e]]++] = e;
+  std::vector<oi::LtEdge> iv((size_t)std::max<int64_t>(m, 1));
+  for (int64_t v = 0; v < n; ++v) {
+    double c = 0.0;
+    uint64_t prev = 0;
+    for (int64_t q = cnt[v]; q < cnt[v + 1]; ++q) {
+      const int64_t e = ord[q];
+      c = c + (double)g->p[e];
+      if (c > 1.0 + 1e-6) return fail(OI_EINVAL, "LT model: in-weights of a node sum above 1");
+      const uint64_t t = (uint64_t)((c < 1.0 ? c : 1.0) * 4294967296.0);
+      iv[e] = t > prev ? oi::LtEdge{(uint32_t)prev, (uint32_t)(t - 1)} : oi::LtEdge{1u, 0u};
+      prev = t;
+    }
+  }
+  HIP_TRY(g->d_lt.ensure(iv.size() * sizeof(oi::LtEdge)));
+  HIP_TRY(hipMemcpy(g->d_lt.p, iv.data(), iv.size() * sizeof(oi::LtEdge), hipMemcpyHostToDevice));
+  g->d_lt_ok = true;
+  return OI_OK;
+}
+
+// The sampling model of a launch's queries (never mixed in one launch).
+oi_status set_model(const oi_graph* g, oi::SampleLaunch& A, const std::vector<const HostQuery*>& qs) {
+  A.mc = qs.empty() ? 0 : qs[0]->dev.mc;
+  A.lt = qs.empty() ? 0 : qs[0]->dev.lt;
+  for (const HostQuery* q : qs)
+    if (q->dev.mc != A.mc || q->dev.lt != A.lt) return fail(OI_ESTATE, "a launch mixes sampling models");
+  A.lt_iv = g->d_lt.as<oi::LtEdge>();
+  return OI_OK;
+}
+
 // Runs the sampling kernels over `segs` and waits for them.  Y goes to y_dev
 // (indexed by out_off) unless bwd; per-segment sums come back in sums.
 oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, const std::vector<SegReq>& segs,
@@ -641,10 +689,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   oi::SampleLaunch A = make_launch(g, g->d_segs.as<oi::Segment>(), g->d_qs.as<oi::QueryDev>(), (int32_t)ds.size(),
                                    total, seed, y_dev, e_dev, ctl, g->d_sums.as<unsigned long long>());
   const bool is_bwd = bwd != nullptr;
-  // Monte-Carlo queries are never mixed with IICP ones in a launch
-  A.mc = qs.empty() ? 0 : qs[0]->dev.mc;
-  for (const HostQuery* q : qs)
-    if (q->dev.mc != A.mc) return fail(OI_ESTATE, "a launch mixes Monte-Carlo and IICP queries");
+  OI_TRY(set_model(g, A, qs));
   if (is_bwd) {
     // the backward knows every sample's Y, so while the soft cap is on (and
     // the last forward launch had few samples above it) those samples go
@@ -901,6 +946,7 @@ oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
   uint32_t* ydev = g->d_y.as<uint32_t>();
   oi::SampleLaunch A = make_launch(g, S.d_segs.as<oi::Segment>(), S.d_qs.as<oi::QueryDev>(), (int32_t)ns, total,
                                    seed, S.write_y ? ydev : nullptr, nullptr, res, res + S.sums_at());
+  OI_TRY(set_model(g, A, S.qv));
   S.soft_budget = A.soft_budget;
   S.timed = g->timing;
   // every operation of the round, in stream order (the result block is
@@ -1185,13 +1231,19 @@ oi_status init_rsa(Rsa& R, HostQuery* Q, int64_t n, double eps, double delta, in
     R.b = nk;
     R.scale = 1.0;
     R.offset = 0.0;
+  } else if (mode == OI_MODE_SIEA_LT) {
+    // RSA on LT cascade sizes X = |S| + Y over [|S|, n]
+    R.a = kd;
+    R.b = (double)n;
+    R.scale = 1.0;
+    R.offset = kd;
   } else {
     R.a = kd + Q->beta0;
     R.b = kd + Q->beta0 * nk;
     R.scale = Q->beta0;
     R.offset = kd;
   }
-  if (!(R.b > R.a)) {  // Y is always 1 (n - |S| = 1): the mean is the lower bound
+  if (!(R.b > R.a)) {  // a single value is possible (n - |S| = 1, or S = V): the lower bound
     R.r.early = 1;
     R.r.mu = R.a;
     if (mode == OI_MODE_SOIEA) {
@@ -1222,7 +1274,7 @@ oi_status init_rsa(Rsa& R, HostQuery* Q, int64_t n, double eps, double delta, in
 oi_status check_eps_delta(double eps, double delta, int mode) {
   if (!(eps > 0.0 && eps < 1.0)) return fail(OI_EINVAL, "eps must lie in (0, 1)");
   if (!(delta > 0.0 && delta < 0.5)) return fail(OI_EINVAL, "delta must lie in (0, 1/2)");
-  if (mode != OI_MODE_SOIEA && mode != OI_MODE_SIEA) return fail(OI_EINVAL, "unknown mode");
+  if (mode != OI_MODE_SOIEA && mode != OI_MODE_SIEA && mode != OI_MODE_SIEA_LT) return fail(OI_EINVAL, "unknown mode");
   return OI_OK;
 }
 
@@ -1237,8 +1289,11 @@ oi_status upload_graph(oi_graph* g) {
   HIP_TRY(g->d_eg.ensure(eg.size() * sizeof(oi::EdgeGroup)));
   HIP_TRY(hipMemcpy(g->d_eg.p, eg.data(), eg.size() * sizeof(oi::EdgeGroup), hipMemcpyHostToDevice));
   g->d_p_ok = false;
+  g->d_lt_ok = false;
   return OI_OK;
 }
+
+
 
 oi_status validate_probs(const std::vector<float>& p) {
   for (float x : p)
@@ -1431,6 +1486,7 @@ oi_status oi_graph_set_theta(oi_graph* g, const float* theta, int device_ptr) {
   }
   // p goes to the device p array and, as thresholds, to the edge groups
   g->d_p_ok = false;
+  g->d_lt_ok = false;
   HIP_TRY(g->d_p.ensure((size_t)g->m * sizeof(float)));
   HIP_TRY(oi::launch_theta_to_p(th, g->m, g->d_eg.as<oi::EdgeGroup>(), g->d_p.as<float>(), g->stream));
   HIP_TRY(hipStreamSynchronize(g->stream));
@@ -1483,11 +1539,14 @@ oi_status oi_stage1_table(oi_graph* g, const int32_t* seeds, int64_t k, int64_t 
 
 namespace {
 
-// Fixed-count sampling of IICP samples (mc = false) or of classic IC
-// Monte-Carlo cascades (mc = true), in launches of up to round_max.
+enum Model { M_IICP = 0, M_MC = 1, M_LT = 2 };
+
+// Fixed-count sampling of IICP samples, of classic IC Monte-Carlo cascades
+// or of LT-model cascades, in launches of up to round_max.
 oi_status sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
                        uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums,
-                       bool mc) {
+                       Model model) {
+  const bool mc = model != M_IICP;
   if (!g) return fail(OI_EINVAL, "null graph");
   if (stream != 0 && stream != 1) return fail(OI_EINVAL, "stream must be 0 or 1");
   if (first + count < first || first + count > kMaxSample) return fail(OI_ERANGE, "sample range beyond 2^59");
@@ -1502,8 +1561,10 @@ oi_status sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int
   // IICP samples need a non-trivial cascade to exist (beta_0 > 0); a
   // Monte-Carlo cascade is drawn whatever beta_0 is
   if ((mc || Q.beta0 > 0.0) && count > 0) {
+    if (model == M_LT) OI_TRY(ensure_lt(g));
     OI_TRY(upload_query(g, Q));
     Q.dev.mc = mc ? 1 : 0;
+    Q.dev.lt = model == M_LT ? 1 : 0;
     uint32_t* ybuf = y_out;
     if (!ybuf) {
       HIP_TRY(g->d_y.ensure((size_t)std::min<uint64_t>(count, g->round_max) * 4));
@@ -1528,7 +1589,8 @@ oi_status sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int
   r.hT = r.sum_y;
   r.mu = count ? (double)r.sum_y / (double)count : 0.0;
   if (mc) {
-    // the MC_N estimate of I(S): the mean cascade size |S| + mean(M - |S|)
+    // the fixed-count estimate of I(S) from plain cascades (the MC_N of the
+    // IC model, or of the LT model): the mean cascade size |S| + mean(Y)
     r.oi = r.mu;
   } else {
     // the fixed-count estimate of Lemma 2: OI = beta_0 * mean(Y)
@@ -1546,12 +1608,17 @@ extern "C" {
 oi_status oi_sample_fixed(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
                           uint64_t first, uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out,
                           oi_result* sums) {
-  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, false);
+  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, M_IICP);
 }
 
 oi_status oi_sample_mc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
                        uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums) {
-  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, true);
+  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, M_MC);
+}
+
+oi_status oi_sample_lt(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream, uint64_t first,
+                       uint64_t count, uint32_t run_seed, uint32_t* y_out, uint64_t* e_out, oi_result* sums) {
+  return sample_fixed(g, query_id, seeds, k, stream, first, count, run_seed, y_out, e_out, sums, M_LT);
 }
 
 oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t* seeds, int64_t k, int stream,
@@ -1743,7 +1810,11 @@ oi_status oi_estimate_batch(oi_graph* g, int32_t nq, const int64_t* seed_off, co
       out[q].status = st;
       continue;
     }
-    if (qs[q]->beta0 > 0.0) OI_TRY(upload_query(g, *qs[q]));
+    if (qs[q]->beta0 > 0.0) {
+      if (mode == OI_MODE_SIEA_LT) OI_TRY(ensure_lt(g));
+      OI_TRY(upload_query(g, *qs[q]));
+      qs[q]->dev.mc = qs[q]->dev.lt = mode == OI_MODE_SIEA_LT ? 1 : 0;
+    }
     Rsa R;
     R.qi = q;
     OI_TRY(init_rsa(R, qs[q].get(), g->n, eps, delta, mode));

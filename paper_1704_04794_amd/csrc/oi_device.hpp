@@ -53,6 +53,10 @@ struct QueryDev {
   // no Stage 1, every node of S active from the start, Y = the nodes
   // outside S that end active (zero allowed); 0: IICP samples (Alg. 1)
   int32_t mc;
+  // 1 (with mc = 1): the cascades follow the LT model in its live-edge form:
+  // node v keeps the in-edge whose interval of v's cumulative in-weights
+  // holds v's choice word (Philox kind 4, idx v/4, word v%4)
+  int32_t lt;
   // 1: Stage 1 after the selection by skip sampling (long tables): entries
   // with P >= 1/2 ("heavy", listed in `heavy`) by their own coins, the
   // others by one walk per kSkipSeg-entry segment over `skipR`, the product
@@ -61,6 +65,13 @@ struct QueryDev {
   const double* skipR;   // l values (skip only)
   const int32_t* heavy;  // nheavy table indices, ascending (skip only)
   int64_t nheavy;
+};
+
+// LT model: edge e is live iff lo <= W_v <= last for its target v's choice
+// word W_v; an empty interval is stored as lo = 1, last = 0
+struct LtEdge {
+  uint32_t lo;
+  uint32_t last;
 };
 
 constexpr int64_t kSkipSeg = 256;       // entries per skip-sampling segment
@@ -147,6 +158,11 @@ struct SampleLaunch {
   // 1: every query of the launch draws classic Monte-Carlo cascades
   // (QueryDev::mc), which the tiny kernel runs in an instantiation of its own
   int32_t mc;
+  // 1: every query of the launch draws LT-model cascades (QueryDev::lt); the
+  // tiny kernel does not run, the small kernel forwards every sample and the
+  // large kernel runs an instantiation of its own
+  int32_t lt;
+  const LtEdge* lt_iv;             // per edge (LT launches)
 };
 
 // Hash used for the per-query seed set table (built on the host, probed on the device).
@@ -163,5 +179,6 @@ constexpr int KIND_EDGE = 0;
 constexpr int KIND_SELECT = 1;
 constexpr int KIND_STAGE1 = 2;
 constexpr int KIND_SKIP = 3;
+constexpr int KIND_LT = 4;
 
 }  // namespace oi

@@ -149,7 +149,7 @@ def test_rsa_rejects_bad_parameters(P):
         with pytest.raises(P.OiError):
             G.estimate([0], eps, delta)
     with pytest.raises(P.OiError):
-        G.estimate([0], 0.1, 0.1, mode=2)
+        G.estimate([0], 0.1, 0.1, mode=3)
     G.close()
 
 
