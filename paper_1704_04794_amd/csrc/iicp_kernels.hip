@@ -287,8 +287,15 @@ __device__ __forceinline__ void hand_over(bool pred, uint64_t f, unsigned long l
 template <int CAP, bool BWD, bool MC>
 __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   __shared__ int32_t vis_all[4][CAP * 64];
+  // the current segment's CDF and table nodes (tables of 2..TINY_LMAX
+  // entries): the samples a wave starts in an iteration all come from that
+  // segment, and select their first entry in the same iteration
+  __shared__ double cdf_all[4][TINY_LMAX + 1];
+  __shared__ int32_t tv_all[4][TINY_LMAX];
   const int lane = threadIdx.x & 63;
   int32_t* vis = &vis_all[threadIdx.x >> 6][lane];  // entry c of this lane at vis[64 * c]
+  double* wcdf = cdf_all[threadIdx.x >> 6];
+  int32_t* wtv = tv_all[threadIdx.x >> 6];
 
   // lane state; the query's fields are copied into registers when a sample
   // starts, so no iteration re-reads shared structures
@@ -392,6 +399,12 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
           c_smask = Qp->smask;
           c_shash = Qp->shash;
           c_tab = Qp->tab;
+          if (!MC && c_l > 1 && c_l <= (int64_t)TINY_LMAX) {
+            const OI_GLOBAL double* qc = gptr(Qp->cdf);
+            for (int64_t x = lane; x <= c_l; x += 64) wcdf[x] = qc[x];
+            if (lane < c_l) wtv[lane] = tab_v(c_tab, lane);
+            wave_sync();
+          }
           if (!MC && c_l == 1) {
             c_v0 = cptr(c_tab)->v[0];
             c_rb0 = cptr(A.row_ptr)[c_v0];
@@ -540,17 +553,18 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       }
     } else if (st == T_START) {
       // Alg. 1, Stage 1: select and activate the first entry (a single entry is selected whatever U is)
+      // (the lanes in this state started in this iteration, from the
+      // segment whose CDF and nodes the wave holds in LDS; a one-entry table
+      // never comes here)
       int64_t i = 0;
       if (ql > 1) {
-        const QueryDev& Q = A.qs[A.segs[sg].q];
-        const OI_GLOBAL double* cdf = gptr(Q.cdf);  // per-lane: lanes may hold samples of different segments
         const uint64_t a = d.w[0] >> 5, b = d.w[1] >> 6;
         const double U = (double)(a * 67108864ull + b) * (1.0 / 9007199254740992.0);
-        const double t = U * Q.beta0;
+        const double t = U * wcdf[ql];  // beta_0 = CDF_l (Eq. zerop)
         int64_t lo = 0, hi = ql;
         while (lo < hi) {
           const int64_t mid = lo + ((hi - lo) >> 1);
-          if (cdf[mid + 1] > t)
+          if (wcdf[mid + 1] > t)
             hi = mid;
           else
             lo = mid + 1;
@@ -559,7 +573,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         if (lo >= ql) {
           i = -1;
           for (int64_t j = ql - 1; j >= 0; --j)
-            if (cdf[j + 1] > cdf[j]) {
+            if (wcdf[j + 1] > wcdf[j]) {
               i = j;
               break;
             }
@@ -569,7 +583,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
           }
         }
       }
-      const int32_t vi = tab_v(tab, i);
+      const int32_t vi = ql > 1 ? wtv[i] : tab_v(tab, i);
       vis[0] = vi;
       cnt = 1;
       qh = 0;
