@@ -450,12 +450,17 @@ def accuracy_experiment(P, args):
     from oi_inputs.configs import ACCURACY_GRAPHS, ACCURACY_MODELS, accuracy_workload
     from paper_1704_04794_amd.accuracy import accuracy
     rows = []
-    for name in ACCURACY_GRAPHS:
-        for model in ACCURACY_MODELS:
+    graphs = args.accuracy_graphs.split(",") if args.accuracy_graphs else list(ACCURACY_GRAPHS)
+    models = args.accuracy_models.split(",") if args.accuracy_models else list(ACCURACY_MODELS)
+    for name in graphs:
+        for model in models:
             g, sets = accuracy_workload(name, model, args.queries or 1000)
             G = P.Graph.from_inputs(g)
             G.estimate_batch(sets[:4], 0.5, 0.1)  # warm up kernels and workspaces
-            r = accuracy(G, sets)
+            t0 = time.perf_counter()
+            r = accuracy(G, sets, truth_chunk=50,
+                         progress=lambda d, n: log(f"{name} {model}: ground truth {d}/{n} "
+                                                   f"({time.perf_counter() - t0:.0f}s)"))
             G.close()
             row = {"graph": name, "model": model, "n": g.n, "m": g.m, "sets": len(sets),
                    "truth_seconds": r["truth"]["seconds"], "truth_samples": r["truth"]["samples"]}
@@ -489,11 +494,16 @@ def main():
                     help="cl4m: seed sets in the subset (default 32); er2k: seed sets (default 256)")
     ap.add_argument("--no-autotune", action="store_true", help="cl4m: keep the default sampler schedule")
     ap.add_argument("--eps", type=float, default=-1.0, help="cl4m: eps (default: the workload's 0.1)")
+    ap.add_argument("--minimal", action="store_true",
+                    help="cl1m: only the timed estimates (for profiler runs): no spread, gather probe, backward, "
+                         "CPU baseline or batched block")
     ap.add_argument("--no-batched", action="store_true",
                     help="cl1m: skip the batched-vs-single block (er2k and the 4M-node subset)")
     ap.add_argument("--batched-per-stratum", type=int, default=16,
                     help="cl1m: seed sets per stratum (uniform, top-1%%) of the 4M-node subset")
     ap.add_argument("--spread", type=int, default=8, help="cl1m: seed sets of the headline's spread")
+    ap.add_argument("--accuracy-graphs", default="", help="accuracy: comma-separated graphs (default: all)")
+    ap.add_argument("--accuracy-models", default="", help="accuracy: comma-separated edge models (default: all)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first copy 1 GiB device-to-device with torch (a plain copy kernel of known size, "
                          "to scale hardware byte counters)")
@@ -596,6 +606,10 @@ def main():
         "sampler": {k: tm[k] for k in ("tiny_ms", "small_ms", "large_ms", "samples", "handed_small",
                                        "handed_large", "tiny_y", "small_y", "large_y")},
     }
+    if args.minimal:
+        G.close()
+        print(json.dumps(out), flush=True)
+        return
     out["spread"] = seed_spread(P, G, g, eps, delta, args.spread)
     from oi_inputs import top_outdeg_seed_set
     out["stage1_skip"] = stage1_skip_gain(
