@@ -43,38 +43,63 @@ METRIC = "IICP samples/s + GTEPS; seed-set estimates/s batched vs single at ε=0
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_NODE = 16  # row_ptr[u], row_ptr[u+1] (int64) per activated node
 BYTES_PER_EDGE = 8   # col (int32) + coin threshold (uint32) per examined edge
+# Algorithmic vector ALU work, in 32-bit lane operations of this ISA: one
+# Philox4x32-10 draw is 10 rounds of two 32x32->64 products (one multiply-add
+# with a 64-bit result each) and two three-input exclusive ors (the key
+# schedule is the same for every lane: scalar work), 40 operations for four
+# coin words.  A coin (Alg. 1: one per Stage-1 entry after the selected one
+# and per out-edge of an activated node) is a quarter draw and a compare; the
+# selection of a sample's first entry, needed only when the Stage-1 table
+# has more than one entry, is one draw.
+PHILOX_OPS = 10 * (2 + 2)
+OPS_PER_COIN = PHILOX_OPS / 4 + 1
+OPS_PER_SELECTION = PHILOX_OPS
+# MI355X vector ALU peak for 32-bit integer operations: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz (one wave64 instruction per CU per clock; the 157.3 TFLOP/s
+# fp32 figure counts an FMA as two and packed pairs as two)
+ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
 
 
-# HBM bytes per tiny_kernel launch on the default workload, from two
-# rocprofv3 counter passes: FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the scales a
-# 1 GiB device copy gives those counters), mean over the 7 launches of one
-# estimate.  Reported only while the kernel sources (their code, comments
-# aside) hash to what was measured and an estimate takes as many launches.
-TRAFFIC = {"sources_sha1": "066abc9d3356e06a15e5e4fb4ca9964402c7d8d2", "kernel": "tiny_kernel",
-           "launches_per_estimate": 7, "bytes_per_launch": 2563694694.4, "l2_hit_rate": 0.785}
+# Counter figures for tiny_kernel on the default workload (rocprofv3 --pmc
+# passes over `bench.py --minimal --warmup 1 --steps 2`): HBM bytes per launch
+# = FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 (the scales a 1 GiB device copy gives
+# those counters), the L2 hit rate, VALU busy (percent of the active cycles
+# the vector ALUs issued), and VALU instructions per examined edge
+# (SQ_INSTS_VALU x 64 lanes over the launch's examined edges); means over the
+# launches of one estimate.  Reported only while the sampler's source up to
+# the small-sample kernel (its code, comments aside) and the device header
+# hash to what was measured, and an estimate takes as many launches.
+COUNTERS = {"sources_sha1": "471c0de0e38da36d433fef0437f5ce2c504bd0eb", "kernel": "tiny_kernel",
+            "launches_per_estimate": 7, "bytes_per_launch": 2.0 * 2186.238 * 1024 + 1.0 * 2498611.089 * 1024,
+            "l2_hit_rate": 0.785, "valu_busy": 0.759, "valu_lane_ops_per_edge": 120.6}
 KERNEL_SOURCES = ("paper_1704_04794_amd/csrc/iicp_kernels.hip", "paper_1704_04794_amd/csrc/oi_device.hpp")
+TINY_REGION_END = "template <int K, int HCAP, int RCAP, int R, bool BWD>\n__global__ void __launch_bounds__(256) small_kernel"
 
 
 def kernel_sources_sha1():
-    """SHA-1 of the kernel sources with comments and blank space removed, so
-    that only a change of code (not of its comments) voids the figure."""
+    """SHA-1 of the tiny sampler's sources (the kernel file up to the
+    small-sample kernel, and the device header) with comments and blank space
+    removed, so that only a change of its code voids the counter figures."""
     import hashlib
     import re
     h = hashlib.sha1()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, f), encoding="utf-8") as fh:
             text = fh.read()
+        if f.endswith(".hip"):
+            end = text.find(TINY_REGION_END)
+            text = text[:end] if end >= 0 else text
         text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
         text = re.sub(r"//[^\n]*", " ", text)
         h.update(" ".join(text.split()).encode())
     return h.hexdigest()
 
 
-def measured_traffic(kernel, launches_per_estimate):
-    if (kernel_sources_sha1() != TRAFFIC["sources_sha1"] or kernel != TRAFFIC["kernel"]
-            or launches_per_estimate != TRAFFIC["launches_per_estimate"]):
+def measured_counters(kernel, launches_per_estimate):
+    if (COUNTERS["sources_sha1"] is None or kernel_sources_sha1() != COUNTERS["sources_sha1"]
+            or kernel != COUNTERS["kernel"] or launches_per_estimate != COUNTERS["launches_per_estimate"]):
         return None
-    return TRAFFIC["bytes_per_launch"]
+    return COUNTERS
 
 
 def log(msg):
@@ -569,15 +594,34 @@ def main():
     dt = time.perf_counter() - t0
     tm = G.timing()
     G.timing(False)
-    # roofline of the kernel that took the most time: the bytes it must read
-    # (a row_ptr pair per activated node, col + p per examined edge) over its
-    # event-timed duration
+    # roofline of the kernel that took the most time: its algorithmic ALU
+    # operations (a coin per examined edge, a selection draw per sample) over
+    # its event-timed duration, against the vector ALU peak; the bytes it
+    # must read over the same time are reported beside it
     kern = max(("tiny", "small", "large"), key=lambda k: tm[f"{k}_ms"])
-    kbytes = BYTES_PER_NODE * tm[f"{kern}_y"] + BYTES_PER_EDGE * tm[f"{kern}_edges"]
     launches = max(tm["launches"], 1)
     lpe = tm["launches"] / args.steps
     avg_ms = tm[f"{kern}_ms"] / launches
-    achieved = (kbytes / launches) / (avg_ms * 1e-3) / 1e9 if avg_ms > 0 else 0.0
+    kbytes = BYTES_PER_NODE * tm[f"{kern}_y"] + BYTES_PER_EDGE * tm[f"{kern}_edges"]
+    sel = tm["samples"] if (kern == "tiny" and res and res["l"] > 1) else 0
+    kops = OPS_PER_COIN * tm[f"{kern}_edges"] + OPS_PER_SELECTION * sel
+    sec = avg_ms * 1e-3
+    achieved = (kops / launches) / sec / 1e12 if avg_ms > 0 else 0.0
+    alg_gbps = (kbytes / launches) / sec / 1e9 if avg_ms > 0 else 0.0
+    cnt = measured_counters(f"{kern}_kernel", lpe)
+    coin = G.coin_probe(1 << 22, 64)
+    coins_per_s = tm[f"{kern}_edges"] / (tm[f"{kern}_ms"] * 1e-3) if tm[f"{kern}_ms"] > 0 else 0.0
+    roofline = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK_TOPS, "unit": "TOP/s",
+                "frac": achieved / ALU_PEAK_TOPS, "traffic": cnt["bytes_per_launch"] if cnt else None,
+                "kernel": f"{kern}_kernel", "avg_launch_ms": avg_ms, "launches": tm["launches"],
+                "ops_per_launch": kops / launches, "ops_per_coin": OPS_PER_COIN,
+                "valu_busy": cnt["valu_busy"] if cnt else None,
+                "valu_lane_ops_per_edge": cnt["valu_lane_ops_per_edge"] if cnt else None,
+                "l2_hit_rate": cnt["l2_hit_rate"] if cnt else None,
+                "hbm_gbps": cnt["bytes_per_launch"] / sec / 1e9 if cnt and avg_ms > 0 else None,
+                "algorithmic_bytes_per_launch": kbytes / launches, "algorithmic_gbps": alg_gbps,
+                "coin_ceiling_words_per_s": coin["words_per_s"],
+                "frac_of_coin_ceiling": coins_per_s / coin["words_per_s"] if coin["words_per_s"] > 0 else None}
     out = {
         "metric": METRIC,
         "value": tot_samples / dt,
@@ -598,11 +642,7 @@ def main():
         "estimates_per_s": args.steps / dt,
         "samples_per_step": tot_samples / args.steps,
         "oi": res["oi"] if res else None,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(f"{kern}_kernel", lpe),
-                     "l2_hit_rate": TRAFFIC["l2_hit_rate"] if measured_traffic(f"{kern}_kernel", lpe) else None,
-                     "kernel": f"{kern}_kernel", "avg_launch_ms": avg_ms, "launches": tm["launches"],
-                     "bytes_per_launch": kbytes / launches},
+        "roofline": roofline,
         "sampler": {k: tm[k] for k in ("tiny_ms", "small_ms", "large_ms", "samples", "handed_small",
                                        "handed_large", "tiny_y", "small_y", "large_y")},
     }
@@ -617,7 +657,7 @@ def main():
         top_outdeg_seed_set(g, 1000, 7), 1 << 18, qid=99)
     gr = gather_roofline(G)
     out["roofline"]["measured_gather_gbps"] = gr["gbps"]
-    out["roofline"]["frac_of_measured_gather"] = achieved / gr["gbps"] if gr["gbps"] > 0 else None
+    out["roofline"]["frac_of_measured_gather"] = alg_gbps / gr["gbps"] if gr["gbps"] > 0 else None
     out["roofline"]["gather_probe"] = {"nodes": 1 << 26, "edges": gr["edges"], "ms": gr["ms"]}
     G.close()
     if not args.no_backward:

@@ -355,6 +355,20 @@ oi_status oi_variant_info(int variant, int* slots_per_wave, int* hash_cap, int* 
 oi_status oi_gather_probe(oi_graph* g, uint64_t count, uint32_t seed, uint64_t* useful_bytes, uint64_t* edges,
                           double* ms);
 
+/* Measurement aid, outside the method: the rate at which this GPU produces
+ * the samplers' coins (Alg. 1 draws one uniform word per Stage-1 entry and
+ * per probed edge; here one Philox4x32-10 draw of four words per edge group,
+ * keyed and counted exactly as the samplers' edge coins: key (qid, seed),
+ * kind 0, stream 0, sample s, group g).  Draws every group g in
+ * [0, groups_per_sample) of every sample s in [0, samples) and compares its
+ * four words with the fixed thresholds 0x19999999, 0x028F5C28, 0x00418937 and
+ * 0x80000000 (word b against threshold b), with no loads, queues or visited
+ * sets.  Outputs: live = words below their threshold (a checksum of the
+ * draws), ms = kernel time (HIP events on the graph's stream).  samples in
+ * [1, 2^40] and groups_per_sample in [1, 4096], else OI_ERANGE. */
+oi_status oi_coin_probe(oi_graph* g, uint64_t samples, uint32_t groups_per_sample, uint32_t seed, uint32_t qid,
+                        uint64_t* live, double* ms);
+
 const char* oi_last_error(void);
 
 #ifdef __cplusplus

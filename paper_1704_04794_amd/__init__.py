@@ -10,7 +10,7 @@ import numpy as np
 
 from ._binding import (  # noqa: F401
     LIB_PATH, OI_MODE_SIEA, OI_MODE_SIEA_LT, OI_MODE_SOIEA, OI_PARAM_P, OI_PARAM_THETA, OiError, oi_autotune, oi_backward,
-    oi_gather_probe,
+    oi_coin_probe, oi_gather_probe,
     oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
     oi_graph_set_theta, oi_last_error,
     oi_num_variants, oi_sample_fixed, oi_sample_fixed_noalloc, oi_sample_lt, oi_sample_mc, oi_set_pipeline, oi_set_routing, oi_set_stage1_skip, oi_set_stream, oi_set_tuning, oi_stage1_table,
@@ -128,6 +128,11 @@ class Graph:
         """Random-read bandwidth of this graph's CSR under the samplers' access
         pattern (no coins or visited sets): dict(useful_bytes, edges, ms, gbps)."""
         return oi_gather_probe(self.h, count, seed)
+
+    def coin_probe(self, samples, groups_per_sample, seed=0, query_id=0):
+        """Rate at which the GPU draws and tests the samplers' edge coins alone
+        (no loads, queues or visited sets): dict(live, words, ms, words_per_s)."""
+        return oi_coin_probe(self.h, samples, groups_per_sample, seed, query_id)
 
     def autotune(self, seed_sets, pilot=1 << 16, query_ids=None, run_seed=RUN_SEED):
         """Time the sampler's schedules on a pilot of up to four of the seed

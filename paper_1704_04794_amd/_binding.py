@@ -95,6 +95,7 @@ def _load():
         "oi_set_tuning": [vp, ci, ci, ci, ci, i64],
         "oi_variant_info": [ci, P(ci), P(ci), P(ci), P(ci)],
         "oi_gather_probe": [vp, u64, u32, P(u64), P(u64), P(dbl)],
+        "oi_coin_probe": [vp, u64, u32, u32, u32, P(u64), P(dbl)],
         "oi_set_routing": [vp, ci, i64],
         "oi_set_pipeline": [vp, ci],
         "oi_set_stage1_skip": [vp, i64],
@@ -320,3 +321,13 @@ def oi_gather_probe(g, count, seed=0):
                                                    C.byref(t)))
     return dict(useful_bytes=b.value, edges=e.value, ms=t.value,
                 gbps=b.value / (t.value * 1e-3) / 1e9 if t.value > 0 else 0.0)
+
+
+def oi_coin_probe(g, samples, groups_per_sample, seed=0, qid=0):
+    """Coin-generation rate probe: dict(live, words, ms, words_per_s)."""
+    live, t = C.c_uint64(), C.c_double()
+    _check("oi_coin_probe", _lib.oi_coin_probe(g, int(samples), int(groups_per_sample), int(seed) & 0xFFFFFFFF,
+                                               int(qid) & 0xFFFFFFFF, C.byref(live), C.byref(t)))
+    words = 4 * int(samples) * int(groups_per_sample)
+    return dict(live=live.value, words=words, ms=t.value,
+                words_per_s=words / (t.value * 1e-3) if t.value > 0 else 0.0)

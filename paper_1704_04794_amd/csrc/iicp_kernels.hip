@@ -1947,6 +1947,34 @@ __global__ void __launch_bounds__(256) gather_probe_kernel(const int64_t* row_pt
   }
 }
 
+// coin probe: the samplers' coin draws (Philox4x32-10 with the edge-coin key
+// and counter layout) and threshold compares alone, without loads, queues or
+// visited sets, to measure the rate at which this chip can produce coins
+// ---------------------------------------------------------------------------
+
+// Lane t draws the coins of samples s = t, t + stride, ...: for each, edge
+// groups 0..groups_per_sample-1 (one draw of four coin words each), every
+// word compared with one of four fixed thresholds.  out[0] += words below
+// their threshold.
+__global__ void __launch_bounds__(256) coin_probe_kernel(uint64_t samples, uint32_t groups_per_sample, uint32_t seed,
+                                                         uint32_t qid, unsigned long long* out) {
+  __shared__ unsigned long long red[4];
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  const uint32_t thr[4] = {0x19999999u, 0x028F5C28u, 0x00418937u, 0x80000000u};
+  uint32_t live = 0;
+  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < samples; s += stride) {
+    for (uint32_t g = 0; g < groups_per_sample; ++g) {
+      const Words w = philox_draw(qid, seed, KIND_EDGE, 0, s, g);
+#pragma unroll
+      for (int b = 0; b < 4; ++b) live += w.w[b] < thr[b] ? 1u : 0u;
+    }
+  }
+  const unsigned long long sum = wave_sum64(live);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(&out[0], red[0] + red[1] + red[2] + red[3]);
+}
+
 // ---------------------------------------------------------------------------
 // host-callable launchers
 // ---------------------------------------------------------------------------
@@ -2151,6 +2179,22 @@ hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, cons
   const uint64_t need = (count + 255) / 256;
   if (blocks > need) blocks = need;
   hipLaunchKernelGGL(gather_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row_ptr, eg, nodes, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_coin_probe(uint64_t samples, uint32_t groups_per_sample, uint32_t seed, uint32_t qid,
+                             unsigned long long* out, int cus, hipStream_t st) {
+  if (samples == 0 || groups_per_sample == 0) return hipSuccess;
+  int bpc = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &bpc, reinterpret_cast<const void*>(&coin_probe_kernel), 256, 0);
+  if (e != hipSuccess) return e;
+  if (bpc < 1) bpc = 1;
+  uint64_t blocks = (uint64_t)bpc * (uint64_t)cus * 4;
+  const uint64_t need = (samples + 255) / 256;
+  if (blocks > need) blocks = need;
+  hipLaunchKernelGGL(coin_probe_kernel, dim3((unsigned)blocks), dim3(256), 0, st, samples, groups_per_sample, seed,
+                     qid, out);
   return hipGetLastError();
 }
 

@@ -44,6 +44,8 @@ hipError_t launch_probe_nodes(const EdgeGroup* eg, int64_t m, uint64_t count, ui
                               hipStream_t st);
 hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, const int32_t* nodes, uint64_t count,
                                unsigned long long* out, int cus, hipStream_t st);
+hipError_t launch_coin_probe(uint64_t samples, uint32_t groups_per_sample, uint32_t seed, uint32_t qid,
+                             unsigned long long* out, int cus, hipStream_t st);
 hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
                             const unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
                             double scale, int theta, float* grad, hipStream_t st);
@@ -1395,6 +1397,38 @@ oi_status oi_gather_probe(oi_graph* g, uint64_t count, uint32_t seed, uint64_t* 
   if (he != hipSuccess) return fail(OI_EHIP, std::string("gather probe failed: ") + hipGetErrorString(he));
   *edges = h[0];
   *useful_bytes = 16ull * count + 8ull * h[0];
+  *ms = (double)t;
+  return OI_OK;
+}
+
+oi_status oi_coin_probe(oi_graph* g, uint64_t samples, uint32_t groups_per_sample, uint32_t seed, uint32_t qid,
+                        uint64_t* live, double* ms) {
+  if (!g || !live || !ms) return fail(OI_EINVAL, "null argument");
+  if (samples == 0 || samples > (1ull << 40) || groups_per_sample == 0 || groups_per_sample > 4096)
+    return fail(OI_ERANGE, "need samples in [1, 2^40] and groups_per_sample in [1, 4096]");
+  DevBuf out;
+  HIP_TRY(out.ensure(sizeof(unsigned long long)));
+  HIP_TRY(hipMemsetAsync(out.p, 0, sizeof(unsigned long long), g->stream));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t he = hipEventCreate(&e1);
+  if (he != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return fail(OI_EHIP, std::string("hipEventCreate failed: ") + hipGetErrorString(he));
+  }
+  he = hipEventRecord(e0, g->stream);
+  if (he == hipSuccess)
+    he = oi::launch_coin_probe(samples, groups_per_sample, seed, qid, out.as<unsigned long long>(), g->cus, g->stream);
+  if (he == hipSuccess) he = hipEventRecord(e1, g->stream);
+  if (he == hipSuccess) he = hipEventSynchronize(e1);
+  float t = 0.f;
+  if (he == hipSuccess) he = hipEventElapsedTime(&t, e0, e1);
+  unsigned long long h = 0;
+  if (he == hipSuccess) he = hipMemcpy(&h, out.p, sizeof(h), hipMemcpyDeviceToHost);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (he != hipSuccess) return fail(OI_EHIP, std::string("coin probe failed: ") + hipGetErrorString(he));
+  *live = h;
   *ms = (double)t;
   return OI_OK;
 }

@@ -78,6 +78,7 @@ def test_null_handles_are_rejected():
     """Entry points given no graph fail with OI_EINVAL instead of touching a GPU."""
     import paper_1704_04794_amd as P
     for call in (lambda: P.oi_gather_probe(None, 1024),
+                 lambda: P.oi_coin_probe(None, 1024, 4),
                  lambda: P.oi_timing_get(None),
                  lambda: P.oi_set_tuning(None, 0),
                  lambda: P.oi_set_routing(None, 0),
