@@ -20,10 +20,11 @@ query.
     python bench.py --workload accuracy [--queries Q]
         relative errors of SOIEA, SIEA, MC_10K and MC_100K against a ground
         truth (Sec. 6.1) on NetHEP- and NetPHY-sized synthetic graphs
-    python bench.py --workload cl100m
+    python bench.py --workload cl100m [--c5-sets K] [--c5-only]
         the 1e8-node / 1.5e9-edge graph: fixed-count throughput for
         |S| = 1, 10, 100, a SIEA estimate, the queue-cap comparison and the
-        backward over all edges
+        backward over all edges; with --c5-sets, SOIEA estimates at the
+        workload's eps = 0.05, delta = 1e-6 for K sets of each size
 """
 from __future__ import annotations
 
@@ -218,6 +219,11 @@ def billion_edge(P, args):
            "workload": f"cl100m: Chung-Lu n=1e8 m={g.m} gamma=2.1 WC p, seed sets of the 256-set list "
                        "(|S| = 1, 10, 100: sets 0, 1, 2)",
            "build_s": build_s, "upload_s": upload_s, "gather_probe_gbps": probe["gbps"], "fixed": []}
+    if args.c5_sets > 0:
+        out["estimates"] = c5_estimates(P, G, g, sets, extra, args.c5_sets)
+    if args.c5_only:
+        G.close()
+        return out
     for qi, N in ((0, 1 << 26), (1, 1 << 20), (2, 1 << 15)):
         S = sets[qi]
         # a warm-up of the same size: the large kernel's queue cap adapts to
@@ -291,6 +297,28 @@ def billion_edge(P, args):
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(g, sets[0], args.cpu_seconds)
     return out
+
+
+def c5_estimates(P, G, g, sets, extra, per_size):
+    """SOIEA estimates at the billion-edge workload's own accuracy (eps =
+    0.05, delta = 1e-6) for the first `per_size` seed sets of each size (1,
+    10, 100) in its seed-set list, one at a time, with each estimate's wall
+    time, sample count and rounds."""
+    eps, delta = extra["eps"], extra["delta"]
+    rows = []
+    for k in sorted(set(int(len(S)) for S in sets)):
+        picks = [qi for qi, S in enumerate(sets) if len(S) == k][:per_size]
+        for qi in picks:
+            t = time.perf_counter()
+            r = G.estimate(sets[qi], eps, delta, mode=P.OI_MODE_SOIEA, query_id=qi)
+            dt = time.perf_counter() - t
+            n_s = r["samples_x"] + r["samples_xp"]
+            row = {"k": k, "query": qi, "eps": eps, "delta": delta, "seconds": dt, "oi": r["oi"], "is": r["is_"],
+                   "beta0": r["beta0"], "samples": n_s, "rounds": r["rounds"], "T1": r["T1"], "T": r["T"],
+                   "samples_per_s": n_s / dt, "gteps": r["edges_examined"] / dt / 1e9}
+            rows.append(row)
+            log(f"estimate |S|={k} set {qi}: {dt:.2f}s OI={r['oi']:.6g} samples={n_s} rounds={r['rounds']}")
+    return rows
 
 
 def batched_vs_single(P, args, per_stratum=False):
@@ -526,6 +554,9 @@ def main():
                     help="cl1m: skip the batched-vs-single block (er2k and the 4M-node subset)")
     ap.add_argument("--batched-per-stratum", type=int, default=16,
                     help="cl1m: seed sets per stratum (uniform, top-1%%) of the 4M-node subset")
+    ap.add_argument("--c5-sets", type=int, default=0,
+                    help="cl100m: SOIEA estimates at eps=0.05, delta=1e-6 for this many sets of each size")
+    ap.add_argument("--c5-only", action="store_true", help="cl100m: only the build, probe and those estimates")
     ap.add_argument("--spread", type=int, default=8, help="cl1m: seed sets of the headline's spread")
     ap.add_argument("--accuracy-graphs", default="", help="accuracy: comma-separated graphs (default: all)")
     ap.add_argument("--accuracy-models", default="", help="accuracy: comma-separated edge models (default: all)")
