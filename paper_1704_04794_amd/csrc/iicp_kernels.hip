@@ -1202,7 +1202,8 @@ __global__ void __launch_bounds__(256) small_kernel(SampleLaunch A) {
 // expands the queue in batches of up to LB * LBN nodes: each thread reads
 // LBN nodes' row bounds, a block scan lays the batch's edge groups out in one
 // index space, and thread t takes groups t, t + LB, ... of it.  After the
-// sample the bits it set (the queue and S) are cleared again.
+// sample the bits it set (the queue and S) are cleared again, or the whole
+// bitmap when the sample was dense.
 constexpr int LB = 256;        // threads of a main-pool block
 constexpr int LB_FULL = 1024;  // threads of a block of the full-queue pass (few, very large samples)
 constexpr int LBN = 4;         // queued nodes per thread per expansion batch
@@ -1571,10 +1572,18 @@ __global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
       atomicAdd(&A.tier_sums[4], (unsigned long long)Yo);
       atomicAdd(&A.tier_sums[5], s_E);
     }
-    for (uint32_t t = tid; t < Y; t += NT) bits[queue[t] >> 5] = 0u;
-    __syncthreads();
-    mark_seed_set<NT>(Q, bits, false, tid);
-    __syncthreads();
+    if ((int64_t)Y * 32 >= A.bits_words) {
+      // a dense sample (at least one activation per 1024 nodes): clearing
+      // the whole bitmap with coalesced full-line stores costs less than a
+      // read-modify-write of one random line per activated node
+      for (int64_t w = tid; w < A.bits_words; w += NT) bits[w] = 0u;
+      __syncthreads();
+    } else {
+      for (uint32_t t = tid; t < Y; t += NT) bits[queue[t] >> 5] = 0u;
+      __syncthreads();
+      mark_seed_set<NT>(Q, bits, false, tid);
+      __syncthreads();
+    }
   }
 }
 
