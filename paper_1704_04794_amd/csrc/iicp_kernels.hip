@@ -2064,6 +2064,23 @@ hipError_t large_occupancy(bool bwd, int* blocks_per_cu) {
   return e;
 }
 
+// Resident 1024-thread blocks per CU of the full-queue pass (the most of its
+// three instantiations).
+hipError_t large_full_occupancy(int* blocks_per_cu) {
+  int a = 0, b = 0, c = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+      &a, reinterpret_cast<const void*>(&large_kernel<false, LB_FULL, false>), LB_FULL, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &b, reinterpret_cast<const void*>(&large_kernel<false, LB_FULL, true>), LB_FULL, 0);
+  if (e == hipSuccess)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+        &c, reinterpret_cast<const void*>(&large_kernel<true, LB_FULL, false>), LB_FULL, 0);
+  int m = a > b ? a : b;
+  *blocks_per_cu = m > c ? m : c;
+  return e;
+}
+
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
   if (bwd)
     hipLaunchKernelGGL((large_kernel<true, LB, false>), dim3(blocks), dim3(LB), 0, st, A);

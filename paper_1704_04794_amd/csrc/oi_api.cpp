@@ -29,6 +29,7 @@ hipError_t launch_small(int v, bool bwd, const SampleLaunch& A, int blocks, hipS
 hipError_t launch_large(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t large_occupancy(bool bwd, int* blocks_per_cu);
 hipError_t launch_large_full(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
+hipError_t large_full_occupancy(int* blocks_per_cu);
 int tiny_cap();
 hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu);
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
@@ -388,7 +389,8 @@ struct BwdBufs {
 // sample that activates more nodes goes to a second pass over blocks with
 // n-entry queues, so the main pool can hold many blocks even for n = 1e8.
 constexpr int64_t kLargeQcap = 1 << 20;
-// blocks of the full-queue pass (at most)
+// blocks of the full-queue pass before its pool is sized (the adaptive cap's
+// first decision); the pool itself holds as many as are resident
 constexpr int kGiantBlocksMax = 64;
 // activations above which a sample counts as giant for the adaptive cap:
 // 2^17, or an eighth of the pool's cap on graphs too small for that
@@ -420,17 +422,19 @@ oi_status ensure_large_pool(oi_graph* g) {
   return OI_OK;
 }
 
-// The pool with n-entry queues, allocated on first need: up to 64 blocks
-// (of 1024 threads: its samples are the largest) within a quarter of free
-// memory and 32 GiB.
+// The pool with n-entry queues, allocated on first need: as many blocks (of
+// 1024 threads: its samples are the largest) as are resident on the GPU,
+// within a quarter of free memory and 64 GiB.
 oi_status ensure_giant_pool(oi_graph* g) {
   if (g->giant_blocks > 0) return OI_OK;
   const int64_t words = (g->n + 31) / 32;
   const double per = (double)words * 4.0 + (double)g->n * 4.0;
   size_t freeb = 0, totalb = 0;
   HIP_TRY(hipMemGetInfo(&freeb, &totalb));
-  const double budget = std::min(32.0 * (1ull << 30), 0.25 * (double)freeb);
-  int blocks = (int)std::min<double>((double)kGiantBlocksMax, std::floor(budget / per));
+  int occ = 0;
+  HIP_TRY(oi::large_full_occupancy(&occ));
+  const double budget = std::min(64.0 * (1ull << 30), 0.25 * (double)freeb);
+  int blocks = (int)std::min<double>((double)std::max(1, occ) * g->cus, std::floor(budget / per));
   if (blocks < 1) return fail(OI_ENOMEM, "no room for a full-size cascade workspace");
   HIP_TRY(g->d_gbits.ensure((size_t)blocks * (size_t)words * 4));
   HIP_TRY(g->d_gqueue.ensure((size_t)blocks * (size_t)g->n * 4));
