@@ -1263,9 +1263,12 @@ __device__ __forceinline__ void push(int32_t* queue, uint32_t* tail, uint32_t qc
   if (pos < qcap) queue[pos] = v;
 }
 
-// LT: the launch's samples are LT-model cascades (forward only).
+// LT: the launch's samples are LT-model cascades (forward only).  The kernel
+// waits on memory most of the time, so it is held to 64 vector registers
+// (eight waves per SIMD, a few values spilled) rather than the 69 that would
+// leave room for seven.
 template <bool BWD, int NT, bool LT>
-__global__ void __launch_bounds__(NT) large_kernel(SampleLaunch A) {
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) large_kernel(SampleLaunch A) {
   __shared__ uint32_t s_tail;
   __shared__ unsigned long long s_E;
   __shared__ uint32_t wtot[NT / 64];
