@@ -265,7 +265,7 @@ oi_status oi_timing_get(oi_graph* g, oi_timing* out);
 oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_chunk, int64_t round_max);
 /* Routing of large samples.  small_direct: 0 (default) lets the small
  * kernel forward the samples the tiny kernel hands over straight to the
- * large kernel when there are no more of them than large-kernel blocks; 1
+ * large kernel when there are at most 128 of them per large-kernel block; 1
  * always forwards them (the small kernel does no sampling); 2 never does;
  * -1 keeps the setting.  The large kernel's main pool has queues of
  * min(n, 2^20) entries per block; a sample that activates more nodes than

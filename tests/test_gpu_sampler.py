@@ -101,7 +101,9 @@ def test_variants_bit_exact(P, variant, tiny):
     g = chung_lu_graph(20000, 200000, 2.1, 7)
     gw = g.with_p(wc_probs(g))
     G = _gpu_graph(P, gw)
-    G.tune(tiny=tiny)
+    # the small kernel samples what it is handed (no direct hand-over), so
+    # that every variant does some of the work
+    G.tune(tiny=tiny, small_direct=2)
     G.timing(True)
     S1 = seed_node_outdeg_ge1(gw, 3)
     _compare(P, gw, S1, 30000, G=G, variant=variant, label=f"cl20k wc |S|=1 tiny={tiny}")
@@ -116,7 +118,7 @@ def test_variants_bit_exact(P, variant, tiny):
     G.close()
     gt = g.with_p(trivalency_probs(g, 5))
     G = _gpu_graph(P, gt)
-    G.tune(tiny=tiny)
+    G.tune(tiny=tiny, small_direct=2)
     _compare(P, gt, S1, 50000, stream=1, first=123_457, G=G, variant=variant, label="cl20k tri X'")
     G.close()
 
