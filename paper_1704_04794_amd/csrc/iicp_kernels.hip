@@ -266,6 +266,8 @@ __device__ __forceinline__ void wave_flush(bool pred, uint32_t seg, unsigned lon
 // tiny_kernel: one sample per lane
 // ---------------------------------------------------------------------------
 constexpr uint32_t TINY_LMAX = 64;  // longest Stage-1 table the tiny kernel takes
+constexpr uint32_t P1_MAXG = 4;     // first-level passes: v_0's row spans at most this many edge groups
+constexpr uint32_t P1_PEND = 256;   // first-level passes: pending samples per wave (a power of two)
 enum : uint32_t { T_IDLE = 0, T_START = 1, T_STAGE1 = 2, T_EXPAND = 3, T_POP = 4 };
 
 // Append the flat indices of the lanes with `pred` to a hand-over list.
@@ -326,6 +328,21 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   // its row bounds: every sample of the segment starts by popping v_0
   int32_t c_v0 = 0, c_v0v = 0;
   int64_t c_rb0 = 0, c_re0 = 0;
+  // first-level passes (the forward IICP kernel; segments whose Stage-1 table
+  // has a single entry v_0 with at most P1_MAXG edge groups): the wave tests
+  // 64 new samples at a time for a live out-edge of v_0, finishes those
+  // without one, and queues the others in a per-wave list of P1_PEND
+  // segment-relative indices, from which its lanes start the cascades.
+  // Everything here is wave-uniform.
+  constexpr bool P1 = !BWD && !MC;
+  __shared__ uint32_t p1thr_all[4][P1 ? 4 * P1_MAXG : 1];
+  __shared__ uint32_t pend_all[4][P1 ? P1_PEND : 1];
+  uint32_t* wp1thr = p1thr_all[threadIdx.x >> 6];
+  uint32_t* wpend = pend_all[threadIdx.x >> 6];
+  bool p1_on = false;
+  uint32_t p1_ng = 0, p1_g0 = 0, p1_mask = 0;
+  unsigned long long p1_deg = 0, p1_n = 0;  // v_0's out-degree; samples finished by passes in this segment
+  uint32_t phead = 0, ptail = 0;            // the list holds [phead, ptail)
   // which per-sample outputs the launch wants, in one scalar word
   const uint32_t outs = __builtin_amdgcn_readfirstlane((A.y_out ? 1u : 0u) | (A.e_out ? 2u : 0u));
   bool exhausted = false;
@@ -366,24 +383,37 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       acc_e += E;
       st = T_IDLE;
     }
-    // (1) idle lanes take the next samples of the wave's chunk, all from the
-    // segment of `cur`
+    // (1) idle lanes take new samples, all from the segment of `cur`: in a
+    // segment that takes first-level passes (below), samples that a pass
+    // found to need the cascade; otherwise the next samples of the chunk
     const unsigned long long idle = __ballot(st == T_IDLE);
     bool started = false;
-    if (idle && !exhausted) {
-      if (cur >= cend) {
-        unsigned long long c = 0;
-        if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
-        c = uniform64(__shfl(c, 0, 64));
-        if (c >= A.total) {
-          exhausted = true;
-        } else {
-          cur = c;
-          cend = c + A.tiny_chunk < A.total ? c + A.tiny_chunk : A.total;
+    if (idle && !(exhausted && phead == ptail)) {
+      const uint32_t nidle = (uint32_t)__popcll(idle);
+      // a segment's pending samples are started before the wave moves on
+      if ((cur >= cend || cur >= cseg_end) && !exhausted && !(P1 && phead != ptail)) {
+        if (cur >= cend) {
+          unsigned long long c = 0;
+          if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
+          c = uniform64(__shfl(c, 0, 64));
+          if (c >= A.total) {
+            exhausted = true;
+          } else {
+            cur = c;
+            cend = c + A.tiny_chunk < A.total ? c + A.tiny_chunk : A.total;
+          }
         }
-      }
-      if (!exhausted) {
-        if (cur >= cseg_end) {
+        if (!exhausted && cur >= cseg_end) {
+          if (P1 && p1_n) {
+            // the samples the first-level passes finished in the old segment
+            if (lane == 0) {
+              atomicAdd(&A.seg_sums[2 * cseg], p1_n);
+              atomicAdd(&A.seg_sums[2 * cseg + 1], p1_n * p1_deg);
+              atomicAdd(&A.tier_sums[0], p1_n);
+              atomicAdd(&A.tier_sums[1], p1_n * p1_deg);
+            }
+            p1_n = 0;
+          }
           cseg = uniform(find_segment_uniform(A, cur));
           const OI_CONST Segment* Sp = cptr(A.segs) + cseg;
           c_flat0 = Sp->flat0;
@@ -405,6 +435,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
             if (lane < c_l) wtv[lane] = tab_v(c_tab, lane);
             wave_sync();
           }
+          p1_on = false;
           if (!MC && c_l == 1) {
             c_v0 = cptr(c_tab)->v[0];
             c_rb0 = cptr(A.row_ptr)[c_v0];
@@ -414,12 +445,86 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
             // across the loop and no move at each start
             c_v0v = c_v0;
             asm volatile("" : "+v"(c_v0v));
+            const int64_t ng = c_re0 > c_rb0 ? ((c_re0 + 3) >> 2) - (c_rb0 >> 2) : 0;
+            if (P1 && ng <= (int64_t)P1_MAXG) {
+              // v_0's edges, read once per segment: slot x of the row's
+              // groups counts iff it is one of v_0's out-edges and its
+              // target lies outside S (an edge into S activates nothing)
+              p1_on = true;
+              p1_ng = (uint32_t)ng;
+              p1_g0 = (uint32_t)(c_rb0 >> 2);
+              p1_deg = (unsigned long long)(c_re0 - c_rb0);
+              bool counted = false;
+              if (lane < 4 * (int)P1_MAXG) {
+                uint32_t thr = 0;
+                const int64_t e = 4 * (int64_t)p1_g0 + lane;
+                if (e >= c_rb0 && e < c_re0) {
+                  const OI_GLOBAL EdgeGroup* grp = gptr(A.eg) + (e >> 2);
+                  const int32_t tgt = grp->v[e & 3];
+                  thr = grp->thr[e & 3];
+                  counted = !in_seed_fields(c_k, c_s0, c_smask, c_shash, tgt);
+                }
+                wp1thr[lane] = thr;
+              }
+              p1_mask = (uint32_t)__ballot(counted);
+              wave_sync();
+            }
           }
         }
+      }
+      while (P1 && p1_on && ptail - phead < nidle && cur < (cend < cseg_end ? cend : cseg_end)) {
+        // a first-level pass over the next (up to) 64 samples, one per lane:
+        // v_0 is activated (the single entry is selected whatever U is, and
+        // no entry follows), and its out-edges' coins are drawn; a sample in
+        // which none of them is live into a node outside S is finished here
+        // (Y = 1, E = deg(v_0)), the others are queued for the cascade
+        {
+          const uint64_t lim = cend < cseg_end ? cend : cseg_end;
+          const uint32_t take = lim - cur < 64ull ? (uint32_t)(lim - cur) : 64u;
+          const bool valid = (uint32_t)lane < take;
+          const uint64_t off = cur - c_flat0 + (uint64_t)lane;
+          const uint64_t ps = c_first + off;
+          uint32_t pseed = A.seed;
+          asm volatile("" : "+s"(pseed));
+          bool live = false;
+#pragma unroll 1
+          for (uint32_t gi = 0; gi < p1_ng; ++gi) {
+            const Words d = philox_draw(c_qid, pseed, KIND_EDGE, c_stream, ps, (uint64_t)(p1_g0 + gi));
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const uint32_t slot = 4 * gi + (uint32_t)b;
+              if ((p1_mask >> slot) & 1u) live |= edge_live(d.w[b], wp1thr[slot]);
+            }
+          }
+          const bool done = valid && !live;
+          const bool more = valid && live;
+          if (done) {
+            if (o & 1u) A.y_out[c_out + off] = 1u;
+            if (o & 2u) A.e_out[c_out + off] = p1_deg;
+          }
+          const unsigned long long dm = __ballot(done), mm = __ballot(more);
+          p1_n += (unsigned long long)__popcll(dm);
+          if (more) wpend[(ptail + lane_prefix(mm)) & (P1_PEND - 1)] = (uint32_t)off;
+          ptail += (uint32_t)__popcll(mm);
+          wave_sync();
+          cur += take;
+        }
+      }
+      if (P1 && phead != ptail) {
+        // pending samples of the current segment go to idle lanes
+        const uint32_t npend = ptail - phead;
+        const uint32_t take = npend < nidle ? npend : nidle;
+        const uint32_t rank = lane_prefix(idle);
+        if (st == T_IDLE && rank < take) {
+          f = c_flat0 + wpend[(phead + rank) & (P1_PEND - 1)];
+          st = T_START;
+          started = true;
+        }
+        phead += take;
+      } else if (!exhausted && !(P1 && p1_on)) {
         const uint64_t lim = cend < cseg_end ? cend : cseg_end;
         const uint64_t room = lim - cur;
-        const uint32_t want = (uint32_t)__popcll(idle);
-        const uint32_t take = room < (uint64_t)want ? (uint32_t)room : want;
+        const uint32_t take = room < (uint64_t)nidle ? (uint32_t)room : nidle;
         const uint32_t rank = lane_prefix(idle);
         if (st == T_IDLE && rank < take) {
           f = cur + rank;
@@ -430,7 +535,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       }
     }
     if (__ballot(st != T_IDLE) == 0ull) {
-      if (exhausted) break;
+      if (exhausted && phead == ptail) break;
       continue;
     }
     // (2) new samples copy their (common) segment's and query's fields.  Long
@@ -667,6 +772,12 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     hand_over(pass_on, f, A.list1, A.nlist1, lane);
   }
   wave_flush(acc_seg != 0xFFFFFFFFu, acc_seg, acc_y, acc_e, A.seg_sums, A.tier_sums, lane);
+  if (P1 && p1_n && lane == 0) {
+    atomicAdd(&A.seg_sums[2 * cseg], p1_n);
+    atomicAdd(&A.seg_sums[2 * cseg + 1], p1_n * p1_deg);
+    atomicAdd(&A.tier_sums[0], p1_n);
+    atomicAdd(&A.tier_sums[1], p1_n * p1_deg);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -270,3 +270,55 @@ def test_routing_and_capped_queues_bit_exact(P, small_direct, qcap):
     got = grad.cpu().numpy().astype(np.float64)
     assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
     G.close()
+
+
+def test_single_entry_tables_bit_exact(P):
+    """Seed sets whose Stage-1 table has one entry v_0 (the one-sample-per-lane
+    kernel tests each sample's out-edges of v_0 in a first pass and runs the
+    cascade only for samples with a live one): v_0's row inside one edge
+    group, across two and four groups, longer than four groups, empty, with
+    edges back into S, with p = 1 edges, and with several seeds.  Y and E
+    bit-exact against the oracle, and the estimate's sums equal."""
+    rng = np.random.default_rng(11)
+    n = 200
+    src, dst = [], []
+    # seeds 0, 1 and 2 point only at node 3 (v_0 for S = {0}, {0, 1}, {0, 1, 2})
+    for s_ in (0, 1, 2):
+        src.append(s_)
+        dst.append(3)
+    # node 3: edges back into {0, 1, 2} and out to 10 nodes, starting at edge id 3
+    for t in (0, 1, 2, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19):
+        src.append(3)
+        dst.append(t)
+    # node 4 -> node 5 (a row of 6 edges, misaligned), node 6 -> node 7 (20 edges), node 8 -> node 9 (no out-edges)
+    for a, b, d in ((4, 5, 6), (6, 7, 20), (8, 9, 0)):
+        src.append(a)
+        dst.append(b)
+        for t in rng.choice(np.arange(20, n), size=d, replace=False):
+            src.append(b)
+            dst.append(int(t))
+    # a random sparse remainder so that cascades continue
+    for u in range(20, n):
+        for t in rng.choice(n, size=3, replace=False):
+            if t != u:
+                src.append(u)
+                dst.append(int(t))
+    src, dst = np.array(src), np.array(dst)
+    key = src * n + dst
+    _, keep = np.unique(key, return_index=True)
+    src, dst = src[np.sort(keep)], dst[np.sort(keep)]
+    p = rng.choice(np.array([0.05, 0.2, 0.5, 1.0], np.float32), size=src.size, p=[0.5, 0.3, 0.15, 0.05])
+    g = graph_from_edges(n, src, dst, p.astype(np.float32))
+    G = _gpu_graph(P, g)
+    for qid, S in enumerate(([0], [0, 1], [0, 1, 2], [4], [6], [8], [3])):
+        tab = O.stage1(g, S)
+        r = _compare(P, g, S, 40_000, qid=qid, G=G, label=f"single-entry S={S} l={tab['l']}")
+        _compare(P, g, S, 30_000, qid=qid, stream=1, first=987_654_321, G=G, label=f"single-entry S={S} X'")
+        if S != [3]:
+            assert tab["l"] == 1 and r["l"] == 1
+    a = G.estimate([0, 1], 0.1, 0.05, query_id=9)
+    b = O.estimate(g, [0, 1], 0.1, 0.05, 0, 9, RUN_SEED)
+    for f in ("T1", "h1", "nsigma", "D", "T", "hT"):
+        assert a[f] == b["rsa"][f], (f, a[f], b["rsa"][f])
+    assert a["oi"] == b["oi"]
+    G.close()
