@@ -534,10 +534,9 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
         cur += take;
       }
     }
-    if (__ballot(st != T_IDLE) == 0ull) {
-      if (exhausted && phead == ptail) break;
-      continue;
-    }
+    const bool busy = __ballot(st != T_IDLE) != 0ull;
+    if (!busy && exhausted && phead == ptail) break;
+    if (busy) {
     // (2) new samples copy their (common) segment's and query's fields.  Long
     // Stage-1 tables (and, in the backward, samples known to be large) go
     // straight to the small kernel.
@@ -770,6 +769,7 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       }
     }
     hand_over(pass_on, f, A.list1, A.nlist1, lane);
+    }
   }
   wave_flush(acc_seg != 0xFFFFFFFFu, acc_seg, acc_y, acc_e, A.seg_sums, A.tier_sums, lane);
   if (P1 && p1_n && lane == 0) {
