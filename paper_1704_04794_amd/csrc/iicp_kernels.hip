@@ -22,6 +22,7 @@
 // every coin is a pure function of (query, stream, sample, edge id): the set
 // of activated nodes is the closure of the Stage-1 set under live edges,
 // whatever order the edges are examined in.
+#include <type_traits>
 #include "oi_device.hpp"
 
 namespace oi {
@@ -266,7 +267,7 @@ __device__ __forceinline__ void wave_flush(bool pred, uint32_t seg, unsigned lon
 // tiny_kernel: one sample per lane
 // ---------------------------------------------------------------------------
 constexpr uint32_t TINY_LMAX = 64;  // longest Stage-1 table the tiny kernel takes
-constexpr uint32_t P1_MAXG = 4;     // first-level passes: v_0's row spans at most this many edge groups
+constexpr uint32_t P1_MAXG = 16;    // first-level passes: v_0's row spans at most this many edge groups
 constexpr uint32_t P1_PEND = 256;   // first-level passes: pending samples per wave (a power of two)
 enum : uint32_t { T_IDLE = 0, T_START = 1, T_STAGE1 = 2, T_EXPAND = 3, T_POP = 4 };
 
@@ -283,11 +284,26 @@ __device__ __forceinline__ void hand_over(bool pred, uint64_t f, unsigned long l
   }
 }
 
+// Wave-uniform state of the tiny kernel's first-level passes: whether the
+// current segment takes them, v_0's edge groups (count, first) and counted
+// slots, v_0's out-degree, the samples the passes finished in the segment,
+// and the pending list's bounds [head, tail).
+struct FirstLevel {
+  bool on;
+  uint32_t ng, g0;
+  unsigned long long mask, deg, n;
+  uint32_t head, tail;
+};
+struct NoFirstLevel {};
+
 // MC: the launch's samples are classic Monte-Carlo cascades (Sec. 2.3), a
 // separate instantiation so that the IICP loop carries none of their
-// bookkeeping.
-template <int CAP, bool BWD, bool MC>
-__global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
+// bookkeeping.  PASS: the forward IICP instantiation with first-level passes.
+// Each instantiation is given the occupancy it is held to (the pass variant
+// needs more registers; the others keep six waves per SIMD, the forward at
+// the price of a few spilled values).
+template <int CAP, bool BWD, bool MC, bool PASS>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ? 4 : (BWD ? 5 : 6)))) tiny_kernel(SampleLaunch A) {
   __shared__ int32_t vis_all[4][CAP * 64];
   // the current segment's CDF and table nodes (tables of 2..TINY_LMAX
   // entries): the samples a wave starts in an iteration all come from that
@@ -334,15 +350,12 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
   // without one, and queues the others in a per-wave list of P1_PEND
   // segment-relative indices, from which its lanes start the cascades.
   // Everything here is wave-uniform.
-  constexpr bool P1 = !BWD && !MC;
+  constexpr bool P1 = PASS && !BWD && !MC;
   __shared__ uint32_t p1thr_all[4][P1 ? 4 * P1_MAXG : 1];
   __shared__ uint32_t pend_all[4][P1 ? P1_PEND : 1];
   uint32_t* wp1thr = p1thr_all[threadIdx.x >> 6];
   uint32_t* wpend = pend_all[threadIdx.x >> 6];
-  bool p1_on = false;
-  uint32_t p1_ng = 0, p1_g0 = 0, p1_mask = 0;
-  unsigned long long p1_deg = 0, p1_n = 0;  // v_0's out-degree; samples finished by passes in this segment
-  uint32_t phead = 0, ptail = 0;            // the list holds [phead, ptail)
+  std::conditional_t<P1, FirstLevel, NoFirstLevel> pw{};
   // which per-sample outputs the launch wants, in one scalar word
   const uint32_t outs = __builtin_amdgcn_readfirstlane((A.y_out ? 1u : 0u) | (A.e_out ? 2u : 0u));
   bool exhausted = false;
@@ -383,15 +396,166 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
       acc_e += E;
       st = T_IDLE;
     }
-    // (1) idle lanes take new samples, all from the segment of `cur`: in a
-    // segment that takes first-level passes (below), samples that a pass
-    // found to need the cascade; otherwise the next samples of the chunk
     const unsigned long long idle = __ballot(st == T_IDLE);
     bool started = false;
-    if (idle && !(exhausted && phead == ptail)) {
-      const uint32_t nidle = (uint32_t)__popcll(idle);
-      // a segment's pending samples are started before the wave moves on
-      if ((cur >= cend || cur >= cseg_end) && !exhausted && !(P1 && phead != ptail)) {
+    if constexpr (P1) {
+      // (1) idle lanes take new samples, all from the segment of `cur`: in a
+      // segment that takes first-level passes (below), samples that a pass
+      // found to need the cascade; otherwise the next samples of the chunk
+      if (idle && !(exhausted && pw.head == pw.tail)) {
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        // a segment's pending samples are started before the wave moves on
+        if ((cur >= cend || cur >= cseg_end) && !exhausted && !(P1 && pw.head != pw.tail)) {
+          if (cur >= cend) {
+            unsigned long long c = 0;
+            if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
+            c = uniform64(__shfl(c, 0, 64));
+            if (c >= A.total) {
+              exhausted = true;
+            } else {
+              cur = c;
+              cend = c + A.tiny_chunk < A.total ? c + A.tiny_chunk : A.total;
+            }
+          }
+          if (!exhausted && cur >= cseg_end) {
+            if (P1 && pw.n) {
+              // the samples the first-level passes finished in the old segment
+              if (lane == 0) {
+                atomicAdd(&A.seg_sums[2 * cseg], pw.n);
+                atomicAdd(&A.seg_sums[2 * cseg + 1], pw.n * pw.deg);
+                atomicAdd(&A.tier_sums[0], pw.n);
+                atomicAdd(&A.tier_sums[1], pw.n * pw.deg);
+              }
+              pw.n = 0;
+            }
+            cseg = uniform(find_segment_uniform(A, cur));
+            const OI_CONST Segment* Sp = cptr(A.segs) + cseg;
+            c_flat0 = Sp->flat0;
+            c_first = Sp->first;
+            c_out = Sp->out_off;
+            c_stream = Sp->stream;
+            cseg_end = c_flat0 + Sp->count;
+            const OI_CONST QueryDev* Qp = cptr(A.qs) + Sp->q;
+            c_qid = Qp->qid;
+            c_l = Qp->l;
+            c_k = Qp->k;
+            c_s0 = Qp->s0;
+            c_smask = Qp->smask;
+            c_shash = Qp->shash;
+            c_tab = Qp->tab;
+            if (!MC && c_l > 1 && c_l <= (int64_t)TINY_LMAX) {
+              const OI_GLOBAL double* qc = gptr(Qp->cdf);
+              for (int64_t x = lane; x <= c_l; x += 64) wcdf[x] = qc[x];
+              if (lane < c_l) wtv[lane] = tab_v(c_tab, lane);
+              wave_sync();
+            }
+            pw.on = false;
+            if (!MC && c_l == 1) {
+              c_v0 = cptr(c_tab)->v[0];
+              c_rb0 = cptr(A.row_ptr)[c_v0];
+              c_re0 = cptr(A.row_ptr)[c_v0 + 1];
+              // v_0 is only ever stored to LDS: kept in a vector register
+              // (the empty asm places it there) it costs no scalar register
+              // across the loop and no move at each start
+              c_v0v = c_v0;
+              asm volatile("" : "+v"(c_v0v));
+              const int64_t ng = c_re0 > c_rb0 ? ((c_re0 + 3) >> 2) - (c_rb0 >> 2) : 0;
+              if (P1 && ng <= (int64_t)P1_MAXG) {
+                // v_0's edges, read once per segment: slot x (= lane) of the
+                // row's groups counts iff it is one of v_0's out-edges and its
+                // target lies outside S (an edge into S activates nothing).
+                // Passes pay off when samples often end at v_0: taken when
+                // the probability that no counted edge is live is >= 1/5
+                bool counted = false;
+                double dead = 1.0;
+                uint32_t thr = 0;
+                const int64_t e = 4 * (c_rb0 >> 2) + lane;
+                if (lane < 4 * ng && e >= c_rb0 && e < c_re0) {
+                  const OI_GLOBAL EdgeGroup* grp = gptr(A.eg) + (e >> 2);
+                  const int32_t tgt = grp->v[e & 3];
+                  thr = grp->thr[e & 3];
+                  counted = !in_seed_fields(c_k, c_s0, c_smask, c_shash, tgt);
+                  if (counted) dead = thr == kThrAlways ? 0.0 : 1.0 - (double)thr * (1.0 / 4294967296.0);
+                }
+                wp1thr[lane] = thr;
+  #pragma unroll
+                for (int sh = 1; sh < 64; sh <<= 1) dead *= __shfl_xor(dead, sh, 64);
+                pw.on = __builtin_amdgcn_readfirstlane(dead >= 0.2 ? 1 : 0) != 0;
+                pw.ng = (uint32_t)ng;
+                pw.g0 = (uint32_t)(c_rb0 >> 2);
+                pw.deg = (unsigned long long)(c_re0 - c_rb0);
+                pw.mask = __ballot(counted);
+                wave_sync();
+              }
+            }
+          }
+        }
+        while (P1 && pw.on && pw.tail - pw.head < nidle && cur < (cend < cseg_end ? cend : cseg_end)) {
+          // a first-level pass over the next (up to) 64 samples, one per lane:
+          // v_0 is activated (the single entry is selected whatever U is, and
+          // no entry follows), and its out-edges' coins are drawn; a sample in
+          // which none of them is live into a node outside S is finished here
+          // (Y = 1, E = deg(v_0)), the others are queued for the cascade
+          {
+            const uint64_t lim = cend < cseg_end ? cend : cseg_end;
+            const uint32_t take = lim - cur < 64ull ? (uint32_t)(lim - cur) : 64u;
+            const bool valid = (uint32_t)lane < take;
+            const uint64_t off = cur - c_flat0 + (uint64_t)lane;
+            const uint64_t ps = c_first + off;
+            uint32_t pseed = A.seed;
+            asm volatile("" : "+s"(pseed));
+            bool live = false;
+  #pragma unroll 1
+            for (uint32_t gi = 0; gi < pw.ng; ++gi) {
+              const Words d = philox_draw(c_qid, pseed, KIND_EDGE, c_stream, ps, (uint64_t)(pw.g0 + gi));
+  #pragma unroll
+              for (int b = 0; b < 4; ++b) {
+                const uint32_t slot = 4 * gi + (uint32_t)b;
+                if ((pw.mask >> slot) & 1ull) live |= edge_live(d.w[b], wp1thr[slot]);
+              }
+            }
+            const bool done = valid && !live;
+            const bool more = valid && live;
+            if (done) {
+              if (o & 1u) A.y_out[c_out + off] = 1u;
+              if (o & 2u) A.e_out[c_out + off] = pw.deg;
+            }
+            const unsigned long long dm = __ballot(done), mm = __ballot(more);
+            pw.n += (unsigned long long)__popcll(dm);
+            if (more) wpend[(pw.tail + lane_prefix(mm)) & (P1_PEND - 1)] = (uint32_t)off;
+            pw.tail += (uint32_t)__popcll(mm);
+            wave_sync();
+            cur += take;
+          }
+        }
+        if (P1 && pw.head != pw.tail) {
+          // pending samples of the current segment go to idle lanes
+          const uint32_t npend = pw.tail - pw.head;
+          const uint32_t take = npend < nidle ? npend : nidle;
+          const uint32_t rank = lane_prefix(idle);
+          if (st == T_IDLE && rank < take) {
+            f = c_flat0 + wpend[(pw.head + rank) & (P1_PEND - 1)];
+            st = T_START;
+            started = true;
+          }
+          pw.head += take;
+        } else if (!exhausted && !(P1 && pw.on)) {
+          const uint64_t lim = cend < cseg_end ? cend : cseg_end;
+          const uint64_t room = lim - cur;
+          const uint32_t take = room < (uint64_t)nidle ? (uint32_t)room : nidle;
+          const uint32_t rank = lane_prefix(idle);
+          if (st == T_IDLE && rank < take) {
+            f = cur + rank;
+            st = T_START;
+            started = true;
+          }
+          cur += take;
+        }
+      }
+    } else {
+      // (1) idle lanes take the next samples of the wave's chunk, all from the
+      // segment of `cur`
+      if (idle && !exhausted) {
         if (cur >= cend) {
           unsigned long long c = 0;
           if (lane == 0) c = atomicAdd(A.counter, (unsigned long long)A.tiny_chunk);
@@ -403,139 +567,67 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
             cend = c + A.tiny_chunk < A.total ? c + A.tiny_chunk : A.total;
           }
         }
-        if (!exhausted && cur >= cseg_end) {
-          if (P1 && p1_n) {
-            // the samples the first-level passes finished in the old segment
-            if (lane == 0) {
-              atomicAdd(&A.seg_sums[2 * cseg], p1_n);
-              atomicAdd(&A.seg_sums[2 * cseg + 1], p1_n * p1_deg);
-              atomicAdd(&A.tier_sums[0], p1_n);
-              atomicAdd(&A.tier_sums[1], p1_n * p1_deg);
-            }
-            p1_n = 0;
-          }
-          cseg = uniform(find_segment_uniform(A, cur));
-          const OI_CONST Segment* Sp = cptr(A.segs) + cseg;
-          c_flat0 = Sp->flat0;
-          c_first = Sp->first;
-          c_out = Sp->out_off;
-          c_stream = Sp->stream;
-          cseg_end = c_flat0 + Sp->count;
-          const OI_CONST QueryDev* Qp = cptr(A.qs) + Sp->q;
-          c_qid = Qp->qid;
-          c_l = Qp->l;
-          c_k = Qp->k;
-          c_s0 = Qp->s0;
-          c_smask = Qp->smask;
-          c_shash = Qp->shash;
-          c_tab = Qp->tab;
-          if (!MC && c_l > 1 && c_l <= (int64_t)TINY_LMAX) {
-            const OI_GLOBAL double* qc = gptr(Qp->cdf);
-            for (int64_t x = lane; x <= c_l; x += 64) wcdf[x] = qc[x];
-            if (lane < c_l) wtv[lane] = tab_v(c_tab, lane);
-            wave_sync();
-          }
-          p1_on = false;
-          if (!MC && c_l == 1) {
-            c_v0 = cptr(c_tab)->v[0];
-            c_rb0 = cptr(A.row_ptr)[c_v0];
-            c_re0 = cptr(A.row_ptr)[c_v0 + 1];
-            // v_0 is only ever stored to LDS: kept in a vector register
-            // (the empty asm places it there) it costs no scalar register
-            // across the loop and no move at each start
-            c_v0v = c_v0;
-            asm volatile("" : "+v"(c_v0v));
-            const int64_t ng = c_re0 > c_rb0 ? ((c_re0 + 3) >> 2) - (c_rb0 >> 2) : 0;
-            if (P1 && ng <= (int64_t)P1_MAXG) {
-              // v_0's edges, read once per segment: slot x of the row's
-              // groups counts iff it is one of v_0's out-edges and its
-              // target lies outside S (an edge into S activates nothing)
-              p1_on = true;
-              p1_ng = (uint32_t)ng;
-              p1_g0 = (uint32_t)(c_rb0 >> 2);
-              p1_deg = (unsigned long long)(c_re0 - c_rb0);
-              bool counted = false;
-              if (lane < 4 * (int)P1_MAXG) {
-                uint32_t thr = 0;
-                const int64_t e = 4 * (int64_t)p1_g0 + lane;
-                if (e >= c_rb0 && e < c_re0) {
-                  const OI_GLOBAL EdgeGroup* grp = gptr(A.eg) + (e >> 2);
-                  const int32_t tgt = grp->v[e & 3];
-                  thr = grp->thr[e & 3];
-                  counted = !in_seed_fields(c_k, c_s0, c_smask, c_shash, tgt);
-                }
-                wp1thr[lane] = thr;
-              }
-              p1_mask = (uint32_t)__ballot(counted);
+        if (!exhausted) {
+          if (cur >= cseg_end) {
+            cseg = uniform(find_segment_uniform(A, cur));
+            const OI_CONST Segment* Sp = cptr(A.segs) + cseg;
+            c_flat0 = Sp->flat0;
+            c_first = Sp->first;
+            c_out = Sp->out_off;
+            c_stream = Sp->stream;
+            cseg_end = c_flat0 + Sp->count;
+            const OI_CONST QueryDev* Qp = cptr(A.qs) + Sp->q;
+            c_qid = Qp->qid;
+            c_l = Qp->l;
+            c_k = Qp->k;
+            c_s0 = Qp->s0;
+            c_smask = Qp->smask;
+            c_shash = Qp->shash;
+            c_tab = Qp->tab;
+            if (!MC && c_l > 1 && c_l <= (int64_t)TINY_LMAX) {
+              const OI_GLOBAL double* qc = gptr(Qp->cdf);
+              for (int64_t x = lane; x <= c_l; x += 64) wcdf[x] = qc[x];
+              if (lane < c_l) wtv[lane] = tab_v(c_tab, lane);
               wave_sync();
             }
-          }
-        }
-      }
-      while (P1 && p1_on && ptail - phead < nidle && cur < (cend < cseg_end ? cend : cseg_end)) {
-        // a first-level pass over the next (up to) 64 samples, one per lane:
-        // v_0 is activated (the single entry is selected whatever U is, and
-        // no entry follows), and its out-edges' coins are drawn; a sample in
-        // which none of them is live into a node outside S is finished here
-        // (Y = 1, E = deg(v_0)), the others are queued for the cascade
-        {
-          const uint64_t lim = cend < cseg_end ? cend : cseg_end;
-          const uint32_t take = lim - cur < 64ull ? (uint32_t)(lim - cur) : 64u;
-          const bool valid = (uint32_t)lane < take;
-          const uint64_t off = cur - c_flat0 + (uint64_t)lane;
-          const uint64_t ps = c_first + off;
-          uint32_t pseed = A.seed;
-          asm volatile("" : "+s"(pseed));
-          bool live = false;
-#pragma unroll 1
-          for (uint32_t gi = 0; gi < p1_ng; ++gi) {
-            const Words d = philox_draw(c_qid, pseed, KIND_EDGE, c_stream, ps, (uint64_t)(p1_g0 + gi));
-#pragma unroll
-            for (int b = 0; b < 4; ++b) {
-              const uint32_t slot = 4 * gi + (uint32_t)b;
-              if ((p1_mask >> slot) & 1u) live |= edge_live(d.w[b], wp1thr[slot]);
+            if (!MC && c_l == 1) {
+              c_v0 = cptr(c_tab)->v[0];
+              c_rb0 = cptr(A.row_ptr)[c_v0];
+              c_re0 = cptr(A.row_ptr)[c_v0 + 1];
+              // v_0 is only ever stored to LDS: kept in a vector register
+              // (the empty asm places it there) it costs no scalar register
+              // across the loop and no move at each start
+              c_v0v = c_v0;
+              asm volatile("" : "+v"(c_v0v));
             }
           }
-          const bool done = valid && !live;
-          const bool more = valid && live;
-          if (done) {
-            if (o & 1u) A.y_out[c_out + off] = 1u;
-            if (o & 2u) A.e_out[c_out + off] = p1_deg;
+          const uint64_t lim = cend < cseg_end ? cend : cseg_end;
+          const uint64_t room = lim - cur;
+          const uint32_t want = (uint32_t)__popcll(idle);
+          const uint32_t take = room < (uint64_t)want ? (uint32_t)room : want;
+          const uint32_t rank = lane_prefix(idle);
+          if (st == T_IDLE && rank < take) {
+            f = cur + rank;
+            st = T_START;
+            started = true;
           }
-          const unsigned long long dm = __ballot(done), mm = __ballot(more);
-          p1_n += (unsigned long long)__popcll(dm);
-          if (more) wpend[(ptail + lane_prefix(mm)) & (P1_PEND - 1)] = (uint32_t)off;
-          ptail += (uint32_t)__popcll(mm);
-          wave_sync();
           cur += take;
         }
       }
-      if (P1 && phead != ptail) {
-        // pending samples of the current segment go to idle lanes
-        const uint32_t npend = ptail - phead;
-        const uint32_t take = npend < nidle ? npend : nidle;
-        const uint32_t rank = lane_prefix(idle);
-        if (st == T_IDLE && rank < take) {
-          f = c_flat0 + wpend[(phead + rank) & (P1_PEND - 1)];
-          st = T_START;
-          started = true;
-        }
-        phead += take;
-      } else if (!exhausted && !(P1 && p1_on)) {
-        const uint64_t lim = cend < cseg_end ? cend : cseg_end;
-        const uint64_t room = lim - cur;
-        const uint32_t take = room < (uint64_t)nidle ? (uint32_t)room : nidle;
-        const uint32_t rank = lane_prefix(idle);
-        if (st == T_IDLE && rank < take) {
-          f = cur + rank;
-          st = T_START;
-          started = true;
-        }
-        cur += take;
+    }
+    if constexpr (!P1) {
+      if (__ballot(st != T_IDLE) == 0ull) {
+        if (exhausted) break;
+        continue;
       }
     }
-    const bool busy = __ballot(st != T_IDLE) != 0ull;
-    if (!busy && exhausted && phead == ptail) break;
+    // (with first-level passes an idle wave skips the sampling step rather
+    // than restarting the loop: one back-edge keeps the lanes' registers
+    // from being copied between two)
+    const bool busy = P1 ? __ballot(st != T_IDLE) != 0ull : true;
+    if constexpr (P1) {
+      if (!busy && exhausted && pw.head == pw.tail) break;
+    }
     if (busy) {
     // (2) new samples copy their (common) segment's and query's fields.  Long
     // Stage-1 tables (and, in the backward, samples known to be large) go
@@ -772,11 +864,13 @@ __global__ void __launch_bounds__(256) tiny_kernel(SampleLaunch A) {
     }
   }
   wave_flush(acc_seg != 0xFFFFFFFFu, acc_seg, acc_y, acc_e, A.seg_sums, A.tier_sums, lane);
-  if (P1 && p1_n && lane == 0) {
-    atomicAdd(&A.seg_sums[2 * cseg], p1_n);
-    atomicAdd(&A.seg_sums[2 * cseg + 1], p1_n * p1_deg);
-    atomicAdd(&A.tier_sums[0], p1_n);
-    atomicAdd(&A.tier_sums[1], p1_n * p1_deg);
+  if constexpr (P1) {
+    if (pw.n && lane == 0) {
+      atomicAdd(&A.seg_sums[2 * cseg], pw.n);
+      atomicAdd(&A.seg_sums[2 * cseg + 1], pw.n * pw.deg);
+      atomicAdd(&A.tier_sums[0], pw.n);
+      atomicAdd(&A.tier_sums[1], pw.n * pw.deg);
+    }
   }
 }
 
@@ -2145,22 +2239,22 @@ constexpr int TINY_CAP = 16;
 
 int tiny_cap() { return TINY_CAP; }
 
-hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu) {
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(
-      blocks_per_cu,
-      bwd ? reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true, false>)
-          : reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false>),
-      256, 0);
+// the instantiation a launch runs: the backward, Monte-Carlo cascades, or
+// IICP samples with or without first-level passes
+static const void* tiny_fn(bool bwd, const SampleLaunch& A) {
+  if (bwd) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true, false, false>);
+  if (A.mc) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, true, false>);
+  if (A.p1) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, true>);
+  return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, false>);
+}
+
+hipError_t tiny_occupancy(bool bwd, const SampleLaunch& A, int* blocks_per_cu) {
+  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, tiny_fn(bwd, A), 256, 0);
 }
 
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st) {
-  if (bwd)
-    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, true, false>), dim3(blocks), dim3(256), 0, st, A);
-  else if (A.mc)
-    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false, true>), dim3(blocks), dim3(256), 0, st, A);
-  else
-    hipLaunchKernelGGL((tiny_kernel<TINY_CAP, false, false>), dim3(blocks), dim3(256), 0, st, A);
-  return hipGetLastError();
+  void* args[] = {const_cast<SampleLaunch*>(&A)};
+  return hipLaunchKernel(tiny_fn(bwd, A), dim3(blocks), dim3(256), args, 0, st);
 }
 
 hipError_t large_occupancy(bool bwd, int* blocks_per_cu) {

@@ -31,7 +31,7 @@ hipError_t large_occupancy(bool bwd, int* blocks_per_cu);
 hipError_t launch_large_full(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t large_full_occupancy(int* blocks_per_cu);
 int tiny_cap();
-hipError_t tiny_occupancy(bool bwd, int* blocks_per_cu);
+hipError_t tiny_occupancy(bool bwd, const SampleLaunch& A, int* blocks_per_cu);
 hipError_t launch_tiny(bool bwd, const SampleLaunch& A, int blocks, hipStream_t st);
 hipError_t launch_chunk_sums(const uint32_t* y, uint64_t count, uint32_t ch, unsigned long long* out, hipStream_t st);
 hipError_t launch_pair_sq(const uint32_t* y, const void* ps, int32_t nps, uint64_t total, unsigned long long* acc,
@@ -258,6 +258,10 @@ struct HostQuery {
   bool skip = false;
   std::vector<double> R;
   std::vector<int32_t> heavy;
+  // single-entry tables: the probability that none of v_0's out-edges into
+  // nodes outside S is live, when v_0's row spans at most 16 edge groups
+  // (0 otherwise); decides whether the tiny kernel's first-level passes pay
+  double p1_dead = 0.0;
   DevBuf d_cdf, d_tab, d_shash, d_R, d_heavy;
   oi::QueryDev dev{};
 };
@@ -335,6 +339,19 @@ oi_status build_table(const oi_graph* g, const int32_t* seeds, int64_t k, HostQu
     uint32_t h = oi::mix32((uint32_t)s) & Q.smask;
     while (Q.shash[h] >= 0) h = (h + 1) & Q.smask;
     Q.shash[h] = s;
+  }
+  Q.p1_dead = 0.0;
+  if (Q.l == 1) {
+    const int64_t rb = g->row_ptr[Q.v[0]], re = g->row_ptr[Q.v[0] + 1];
+    if (re <= rb || ((re + 3) >> 2) - (rb >> 2) <= 16) {
+      double dead = 1.0;
+      for (int64_t e = rb; e < re; ++e) {
+        if (inS(g->col[e])) continue;
+        const uint32_t t = oi::coin_threshold(g->p[e]);
+        dead *= t == oi::kThrAlways ? 0.0 : 1.0 - (double)t * (1.0 / 4294967296.0);
+      }
+      Q.p1_dead = dead;
+    }
   }
   return OI_OK;
 }
@@ -578,7 +595,7 @@ oi_status launch_tiers(oi_graph* g, oi::SampleLaunch& A, bool is_bwd, hipEvent_t
   const bool tiny = g->use_tiny && !A.lt;
   A.small_from_list1 = tiny ? 1 : 0;
   if (tiny) {
-    HIP_TRY(oi::tiny_occupancy(is_bwd, &bpc));
+    HIP_TRY(oi::tiny_occupancy(is_bwd, A, &bpc));
     if (bpc < 1) bpc = 1;
     const int blocks = (int)std::min<uint64_t>((uint64_t)bpc * (uint64_t)g->cus, std::max<uint64_t>(1, (want_waves + 3) / 4));
     if (g->tiny_chunk == 0) {
@@ -662,12 +679,24 @@ oi_status ensure_lt(oi_graph* g) {
 }
 
 // The sampling model of a launch's queries (never mixed in one launch).
-oi_status set_model(const oi_graph* g, oi::SampleLaunch& A, const std::vector<const HostQuery*>& qs) {
+// The launch's sampling model, and whether the tiny kernel runs with
+// first-level passes: when at least 70% of the launch's samples are expected
+// to end at v_0 of a single-entry table (measured on the 1M-node graph:
+// passes gained 22-25% for seeds at 85-89%, lost 8% at 50%, where the
+// variant's higher register use costs more than the passes save).
+oi_status set_model(const oi_graph* g, oi::SampleLaunch& A, const std::vector<const HostQuery*>& qs,
+                    const std::vector<SegReq>& segs) {
   A.mc = qs.empty() ? 0 : qs[0]->dev.mc;
   A.lt = qs.empty() ? 0 : qs[0]->dev.lt;
   for (const HostQuery* q : qs)
     if (q->dev.mc != A.mc || q->dev.lt != A.lt) return fail(OI_ESTATE, "a launch mixes sampling models");
   A.lt_iv = g->d_lt.as<oi::LtEdge>();
+  double ending = 0.0, total = 0.0;
+  for (const SegReq& r : segs) {
+    ending += (double)r.count * qs[r.q]->p1_dead;
+    total += (double)r.count;
+  }
+  A.p1 = (!A.mc && !A.lt && total > 0.0 && ending >= 0.7 * total) ? 1 : 0;
   return OI_OK;
 }
 
@@ -709,7 +738,7 @@ oi_status run_sampler(oi_graph* g, const std::vector<const HostQuery*>& qs, cons
   oi::SampleLaunch A = make_launch(g, g->d_segs.as<oi::Segment>(), g->d_qs.as<oi::QueryDev>(), (int32_t)ds.size(),
                                    total, seed, y_dev, e_dev, ctl, g->d_sums.as<unsigned long long>());
   const bool is_bwd = bwd != nullptr;
-  OI_TRY(set_model(g, A, qs));
+  OI_TRY(set_model(g, A, qs, segs));
   if (is_bwd) {
     // the backward knows every sample's Y, so while the soft cap is on (and
     // the last forward launch had few samples above it) those samples go
@@ -966,7 +995,7 @@ oi_status enqueue_round(oi_graph* g, RoundSlot& S, uint32_t seed) {
   uint32_t* ydev = g->d_y.as<uint32_t>();
   oi::SampleLaunch A = make_launch(g, S.d_segs.as<oi::Segment>(), S.d_qs.as<oi::QueryDev>(), (int32_t)ns, total,
                                    seed, S.write_y ? ydev : nullptr, nullptr, res, res + S.sums_at());
-  OI_TRY(set_model(g, A, S.qv));
+  OI_TRY(set_model(g, A, S.qv, S.segs));
   S.soft_budget = A.soft_budget;
   S.timed = g->timing;
   // every operation of the round, in stream order (the result block is
@@ -1790,6 +1819,7 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
         A.nbig = nullptr;
         A.soft_cap = (uint32_t)qcap;
         A.soft_budget = 0;
+        A.p1 = Q.p1_dead >= 0.7 ? 1 : 0;
         OI_TRY(launch_tiers(g, A, false, nullptr, st, blocks));
         unsigned long long h[18] = {0};
         HIP_TRY(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));

@@ -163,6 +163,10 @@ struct SampleLaunch {
   // large kernel runs an instantiation of its own
   int32_t lt;
   const LtEdge* lt_iv;             // per edge (LT launches)
+  // 1: the tiny kernel runs its instantiation with first-level passes (chosen
+  // on the host when most of the launch's samples belong to single-entry
+  // Stage-1 tables whose v_0 often activates nothing)
+  int32_t p1;
 };
 
 // Hash used for the per-query seed set table (built on the host, probed on the device).

@@ -276,41 +276,39 @@ def test_single_entry_tables_bit_exact(P):
     """Seed sets whose Stage-1 table has one entry v_0 (the one-sample-per-lane
     kernel tests each sample's out-edges of v_0 in a first pass and runs the
     cascade only for samples with a live one): v_0's row inside one edge
-    group, across two and four groups, longer than four groups, empty, with
-    edges back into S, with p = 1 edges, and with several seeds.  Y and E
-    bit-exact against the oracle, and the estimate's sums equal."""
+    group, across two, four and seven groups, longer than sixteen groups,
+    empty, with edges back into S, with p = 1 edges, and with several seeds.
+    Y and E bit-exact against the oracle, and the estimate's sums equal."""
     rng = np.random.default_rng(11)
-    n = 200
-    src, dst = [], []
+    n = 300
+    edges = []  # (src, dst, p)
+    pick = lambda: float(rng.choice([0.05, 0.2, 0.5, 1.0], p=[0.5, 0.3, 0.15, 0.05]))
     # seeds 0, 1 and 2 point only at node 3 (v_0 for S = {0}, {0, 1}, {0, 1, 2})
     for s_ in (0, 1, 2):
-        src.append(s_)
-        dst.append(3)
-    # node 3: edges back into {0, 1, 2} and out to 10 nodes, starting at edge id 3
+        edges.append((s_, 3, pick()))
+    # node 3: edges back into {0, 1, 2} and out to 10 nodes (edge ids 3..15)
     for t in (0, 1, 2, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19):
-        src.append(3)
-        dst.append(t)
-    # node 4 -> node 5 (a row of 6 edges, misaligned), node 6 -> node 7 (20 edges), node 8 -> node 9 (no out-edges)
-    for a, b, d in ((4, 5, 6), (6, 7, 20), (8, 9, 0)):
-        src.append(a)
-        dst.append(b)
-        for t in rng.choice(np.arange(20, n), size=d, replace=False):
-            src.append(b)
-            dst.append(int(t))
+        edges.append((3, t, pick()))
+    # single-entry seeds a -> b, where b has d out-edges of probability q:
+    # 6 mixed (misaligned), 20 mixed, none, 25 at 0.02 (seven groups, mostly
+    # dead), 70 at 0.01 (more than sixteen groups)
+    for a, b, d, q in ((4, 5, 6, None), (6, 7, 20, None), (8, 9, 0, None), (20, 21, 25, 0.02), (22, 23, 70, 0.01)):
+        edges.append((a, b, pick()))
+        for t in rng.choice(np.arange(30, n), size=d, replace=False):
+            edges.append((b, int(t), pick() if q is None else q))
     # a random sparse remainder so that cascades continue
-    for u in range(20, n):
+    for u in range(30, n):
         for t in rng.choice(n, size=3, replace=False):
             if t != u:
-                src.append(u)
-                dst.append(int(t))
-    src, dst = np.array(src), np.array(dst)
-    key = src * n + dst
-    _, keep = np.unique(key, return_index=True)
-    src, dst = src[np.sort(keep)], dst[np.sort(keep)]
-    p = rng.choice(np.array([0.05, 0.2, 0.5, 1.0], np.float32), size=src.size, p=[0.5, 0.3, 0.15, 0.05])
-    g = graph_from_edges(n, src, dst, p.astype(np.float32))
+                edges.append((u, int(t), pick()))
+    src = np.array([e[0] for e in edges])
+    dst = np.array([e[1] for e in edges])
+    p = np.array([e[2] for e in edges], np.float32)
+    _, keep = np.unique(src * n + dst, return_index=True)
+    keep = np.sort(keep)
+    g = graph_from_edges(n, src[keep], dst[keep], p[keep])
     G = _gpu_graph(P, g)
-    for qid, S in enumerate(([0], [0, 1], [0, 1, 2], [4], [6], [8], [3])):
+    for qid, S in enumerate(([0], [0, 1], [0, 1, 2], [4], [6], [8], [20], [22], [3])):
         tab = O.stage1(g, S)
         r = _compare(P, g, S, 40_000, qid=qid, G=G, label=f"single-entry S={S} l={tab['l']}")
         _compare(P, g, S, 30_000, qid=qid, stream=1, first=987_654_321, G=G, label=f"single-entry S={S} X'")
