@@ -269,6 +269,7 @@ __device__ __forceinline__ void wave_flush(bool pred, uint32_t seg, unsigned lon
 constexpr uint32_t TINY_LMAX = 64;  // longest Stage-1 table the tiny kernel takes
 constexpr uint32_t P1_MAXG = 16;    // first-level passes: v_0's row spans at most this many edge groups
 constexpr uint32_t P1_PEND = 256;   // first-level passes: pending samples per wave (a power of two)
+constexpr uint32_t P1L_MAXL = 16;   // first-level passes: longest Stage-1 table they take
 enum : uint32_t { T_IDLE = 0, T_START = 1, T_STAGE1 = 2, T_EXPAND = 3, T_POP = 4 };
 
 // Append the flat indices of the lanes with `pred` to a hand-over list.
@@ -285,24 +286,26 @@ __device__ __forceinline__ void hand_over(bool pred, uint64_t f, unsigned long l
 }
 
 // Wave-uniform state of the tiny kernel's first-level passes: whether the
-// current segment takes them, v_0's edge groups (count, first) and counted
-// slots, v_0's out-degree, the samples the passes finished in the segment,
-// and the pending list's bounds [head, tail).
+// current segment takes them (and whether its table has several entries),
+// for a single entry v_0 its edge groups (count, first), counted slots and
+// out-degree, the samples the passes finished in the segment with their E
+// sum, and the pending list's bounds [head, tail).
 struct FirstLevel {
-  bool on;
+  bool on, gen;  // passes in this segment; a table of 2..P1L_MAXL entries
   uint32_t ng, g0;
-  unsigned long long mask, deg, n;
+  unsigned long long mask, deg, n, e;  // e: the E sum of the samples finished by passes
   uint32_t head, tail;
 };
 struct NoFirstLevel {};
 
 // MC: the launch's samples are classic Monte-Carlo cascades (Sec. 2.3), a
 // separate instantiation so that the IICP loop carries none of their
-// bookkeeping.  PASS: the forward IICP instantiation with first-level passes.
+// bookkeeping.  PASS: the forward IICP instantiation with first-level passes,
+// over single-entry tables only (1) or over tables of up to P1L_MAXL entries (2).
 // Each instantiation is given the occupancy it is held to (the pass variant
 // needs more registers; the others keep six waves per SIMD, the forward at
 // the price of a few spilled values).
-template <int CAP, bool BWD, bool MC, bool PASS>
+template <int CAP, bool BWD, bool MC, int PASS>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ? 4 : (BWD ? 5 : 6)))) tiny_kernel(SampleLaunch A) {
   __shared__ int32_t vis_all[4][CAP * 64];
   // the current segment's CDF and table nodes (tables of 2..TINY_LMAX
@@ -350,11 +353,20 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
   // without one, and queues the others in a per-wave list of P1_PEND
   // segment-relative indices, from which its lanes start the cascades.
   // Everything here is wave-uniform.
-  constexpr bool P1 = PASS && !BWD && !MC;
+  constexpr bool P1 = PASS != 0 && !BWD && !MC;
+  constexpr bool P1GEN = P1 && PASS == 2;  // passes also over tables of several entries
   __shared__ uint32_t p1thr_all[4][P1 ? 4 * P1_MAXG : 1];
   __shared__ uint32_t pend_all[4][P1 ? P1_PEND : 1];
+  // tables of 2..P1L_MAXL entries: each entry's Stage-1 coin threshold and
+  // its node's row bounds
+  __shared__ uint64_t p1sthr_all[4][P1GEN ? P1L_MAXL : 1];
+  __shared__ uint32_t p1rb_all[4][P1GEN ? P1L_MAXL : 1];
+  __shared__ uint32_t p1re_all[4][P1GEN ? P1L_MAXL : 1];
   uint32_t* wp1thr = p1thr_all[threadIdx.x >> 6];
   uint32_t* wpend = pend_all[threadIdx.x >> 6];
+  uint64_t* wsthr = p1sthr_all[threadIdx.x >> 6];
+  uint32_t* wrb = p1rb_all[threadIdx.x >> 6];
+  uint32_t* wre = p1re_all[threadIdx.x >> 6];
   std::conditional_t<P1, FirstLevel, NoFirstLevel> pw{};
   // which per-sample outputs the launch wants, in one scalar word
   const uint32_t outs = __builtin_amdgcn_readfirstlane((A.y_out ? 1u : 0u) | (A.e_out ? 2u : 0u));
@@ -422,11 +434,12 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
               // the samples the first-level passes finished in the old segment
               if (lane == 0) {
                 atomicAdd(&A.seg_sums[2 * cseg], pw.n);
-                atomicAdd(&A.seg_sums[2 * cseg + 1], pw.n * pw.deg);
+                atomicAdd(&A.seg_sums[2 * cseg + 1], pw.e);
                 atomicAdd(&A.tier_sums[0], pw.n);
-                atomicAdd(&A.tier_sums[1], pw.n * pw.deg);
+                atomicAdd(&A.tier_sums[1], pw.e);
               }
               pw.n = 0;
+              pw.e = 0;
             }
             cseg = uniform(find_segment_uniform(A, cur));
             const OI_CONST Segment* Sp = cptr(A.segs) + cseg;
@@ -450,6 +463,19 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
               wave_sync();
             }
             pw.on = false;
+            pw.gen = false;
+            if (P1GEN && c_l > 1 && c_l <= (int64_t)P1L_MAXL && Qp->p1) {
+              // (the entries' nodes are in wtv already)
+              if (lane < c_l) {
+                wsthr[lane] = tab_thr(c_tab, lane);
+                const int32_t v = wtv[lane];
+                wrb[lane] = (uint32_t)cptr(A.row_ptr)[v];
+                wre[lane] = (uint32_t)cptr(A.row_ptr)[v + 1];
+              }
+              wave_sync();
+              pw.on = true;
+              pw.gen = true;
+            }
             if (!MC && c_l == 1) {
               c_v0 = cptr(c_tab)->v[0];
               c_rb0 = cptr(A.row_ptr)[c_v0];
@@ -464,10 +490,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
                 // v_0's edges, read once per segment: slot x (= lane) of the
                 // row's groups counts iff it is one of v_0's out-edges and its
                 // target lies outside S (an edge into S activates nothing).
-                // Passes pay off when samples often end at v_0: taken when
-                // the probability that no counted edge is live is >= 1/5
+                // Passes are taken when the host found that samples often end
+                // at v_0
                 bool counted = false;
-                double dead = 1.0;
                 uint32_t thr = 0;
                 const int64_t e = 4 * (c_rb0 >> 2) + lane;
                 if (lane < 4 * ng && e >= c_rb0 && e < c_re0) {
@@ -475,12 +500,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
                   const int32_t tgt = grp->v[e & 3];
                   thr = grp->thr[e & 3];
                   counted = !in_seed_fields(c_k, c_s0, c_smask, c_shash, tgt);
-                  if (counted) dead = thr == kThrAlways ? 0.0 : 1.0 - (double)thr * (1.0 / 4294967296.0);
                 }
                 wp1thr[lane] = thr;
-  #pragma unroll
-                for (int sh = 1; sh < 64; sh <<= 1) dead *= __shfl_xor(dead, sh, 64);
-                pw.on = __builtin_amdgcn_readfirstlane(dead >= 0.2 ? 1 : 0) != 0;
+                pw.on = Qp->p1 != 0;
                 pw.ng = (uint32_t)ng;
                 pw.g0 = (uint32_t)(c_rb0 >> 2);
                 pw.deg = (unsigned long long)(c_re0 - c_rb0);
@@ -504,24 +526,75 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
             const uint64_t ps = c_first + off;
             uint32_t pseed = A.seed;
             asm volatile("" : "+s"(pseed));
-            bool live = false;
+            bool need = false;           // the sample needs the cascade
+            unsigned long long eo = 0;   // its E if it ends at its first node
+            if (!P1GEN || !pw.gen) {
   #pragma unroll 1
-            for (uint32_t gi = 0; gi < pw.ng; ++gi) {
-              const Words d = philox_draw(c_qid, pseed, KIND_EDGE, c_stream, ps, (uint64_t)(pw.g0 + gi));
+              for (uint32_t gi = 0; gi < pw.ng; ++gi) {
+                const Words d = philox_draw(c_qid, pseed, KIND_EDGE, c_stream, ps, (uint64_t)(pw.g0 + gi));
   #pragma unroll
-              for (int b = 0; b < 4; ++b) {
-                const uint32_t slot = 4 * gi + (uint32_t)b;
-                if ((pw.mask >> slot) & 1ull) live |= edge_live(d.w[b], wp1thr[slot]);
+                for (int b = 0; b < 4; ++b) {
+                  const uint32_t slot = 4 * gi + (uint32_t)b;
+                  if ((pw.mask >> slot) & 1ull) need |= edge_live(d.w[b], wp1thr[slot]);
+                }
               }
+              eo = pw.deg;
+            } else if constexpr (P1GEN) {
+              // Alg. 1 for a table of several entries: the selection i (as the
+              // state machine makes it; its rare fallback is left to it), the
+              // coins of the later entries, then the coins of v_i's out-edges
+              const Words dsel = philox_draw(c_qid, pseed, KIND_SELECT, c_stream, ps, 0ull);
+              const uint64_t ua = dsel.w[0] >> 5, ub = dsel.w[1] >> 6;
+              const double U = (double)(ua * 67108864ull + ub) * (1.0 / 9007199254740992.0);
+              const double t = U * wcdf[c_l];
+              int64_t lo = 0, hi = c_l;
+              while (lo < hi) {
+                const int64_t mid = lo + ((hi - lo) >> 1);
+                if (wcdf[mid + 1] > t)
+                  hi = mid;
+                else
+                  lo = mid + 1;
+              }
+              need = lo >= c_l;
+              const int64_t i = need ? 0 : lo;
+              for (int64_t g = (i + 1) >> 2; !need && 4 * g < c_l; ++g) {
+                const Words d = philox_draw(c_qid, pseed, KIND_STAGE1, c_stream, ps, (uint64_t)g);
+  #pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                  const int64_t j = 4 * g + b;
+                  if (j > i && j < c_l && (uint64_t)d.w[b] < wsthr[j]) need = true;
+                }
+              }
+              const uint32_t rb = wrb[i], re = wre[i];
+              const uint32_t g0 = rb >> 2, ng = re > rb ? ((re + 3) >> 2) - g0 : 0u;
+              if (ng > P1_MAXG) need = true;
+              for (uint32_t gi = 0; !need && gi < ng; ++gi) {
+                const Words d = philox_draw(c_qid, pseed, KIND_EDGE, c_stream, ps, (uint64_t)(g0 + gi));
+                const OI_GLOBAL char* q = (const OI_GLOBAL char*)(gptr(A.eg) + g0 + gi);
+                const v4i32 tv = *(const OI_GLOBAL v4i32*)q;
+                const v4i32 tp = *(const OI_GLOBAL v4i32*)(q + 16);
+  #pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                  const uint32_t e = 4 * (g0 + gi) + (uint32_t)b;
+                  if (e >= rb && e < re && edge_live(d.w[b], (uint32_t)tp[b]) &&
+                      !in_seed_fields(c_k, c_s0, c_smask, c_shash, tv[b]))
+                    need = true;
+                }
+              }
+              eo = (unsigned long long)(c_l - 1 - i) + (re - rb);
             }
-            const bool done = valid && !live;
-            const bool more = valid && live;
+            const bool done = valid && !need;
+            const bool more = valid && need;
             if (done) {
               if (o & 1u) A.y_out[c_out + off] = 1u;
-              if (o & 2u) A.e_out[c_out + off] = pw.deg;
+              if (o & 2u) A.e_out[c_out + off] = eo;
             }
             const unsigned long long dm = __ballot(done), mm = __ballot(more);
             pw.n += (unsigned long long)__popcll(dm);
+            if (P1GEN && pw.gen)
+              pw.e += uniform64(wave_sum64(done ? eo : 0ull));
+            else
+              pw.e += (unsigned long long)__popcll(dm) * pw.deg;
             if (more) wpend[(pw.tail + lane_prefix(mm)) & (P1_PEND - 1)] = (uint32_t)off;
             pw.tail += (uint32_t)__popcll(mm);
             wave_sync();
@@ -867,9 +940,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ?
   if constexpr (P1) {
     if (pw.n && lane == 0) {
       atomicAdd(&A.seg_sums[2 * cseg], pw.n);
-      atomicAdd(&A.seg_sums[2 * cseg + 1], pw.n * pw.deg);
+      atomicAdd(&A.seg_sums[2 * cseg + 1], pw.e);
       atomicAdd(&A.tier_sums[0], pw.n);
-      atomicAdd(&A.tier_sums[1], pw.n * pw.deg);
+      atomicAdd(&A.tier_sums[1], pw.e);
     }
   }
 }
@@ -2242,10 +2315,11 @@ int tiny_cap() { return TINY_CAP; }
 // the instantiation a launch runs: the backward, Monte-Carlo cascades, or
 // IICP samples with or without first-level passes
 static const void* tiny_fn(bool bwd, const SampleLaunch& A) {
-  if (bwd) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true, false, false>);
-  if (A.mc) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, true, false>);
-  if (A.p1) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, true>);
-  return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, false>);
+  if (bwd) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, true, false, 0>);
+  if (A.mc) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, true, 0>);
+  if (A.p1 == 1) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, 1>);
+  if (A.p1 == 2) return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, 2>);
+  return reinterpret_cast<const void*>(&tiny_kernel<TINY_CAP, false, false, 0>);
 }
 
 hipError_t tiny_occupancy(bool bwd, const SampleLaunch& A, int* blocks_per_cu) {

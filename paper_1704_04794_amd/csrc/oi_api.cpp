@@ -258,9 +258,9 @@ struct HostQuery {
   bool skip = false;
   std::vector<double> R;
   std::vector<int32_t> heavy;
-  // single-entry tables: the probability that none of v_0's out-edges into
-  // nodes outside S is live, when v_0's row spans at most 16 edge groups
-  // (0 otherwise); decides whether the tiny kernel's first-level passes pay
+  // tables of at most 16 entries: the probability that a sample ends at its
+  // first activated node (0 otherwise); decides whether the tiny kernel's
+  // first-level passes pay
   double p1_dead = 0.0;
   DevBuf d_cdf, d_tab, d_shash, d_R, d_heavy;
   oi::QueryDev dev{};
@@ -340,18 +340,26 @@ oi_status build_table(const oi_graph* g, const int32_t* seeds, int64_t k, HostQu
     while (Q.shash[h] >= 0) h = (h + 1) & Q.smask;
     Q.shash[h] = s;
   }
+  // the probability that a sample ends at its first activated node: entry i
+  // selected (Pr[A_i] / beta_0), no later entry live, and no out-edge of
+  // v_i live into a node outside S (rows of more than 16 edge groups count
+  // as never ending there: the passes do not take them)
   Q.p1_dead = 0.0;
-  if (Q.l == 1) {
-    const int64_t rb = g->row_ptr[Q.v[0]], re = g->row_ptr[Q.v[0] + 1];
-    if (re <= rb || ((re + 3) >> 2) - (rb >> 2) <= 16) {
-      double dead = 1.0;
+  if (Q.l >= 1 && Q.l <= 16 && Q.beta0 > 0.0) {
+    double frac = 0.0;
+    for (int64_t i = 0; i < Q.l; ++i) {
+      const int64_t rb = g->row_ptr[Q.v[i]], re = g->row_ptr[Q.v[i] + 1];
+      if (re > rb && ((re + 3) >> 2) - (rb >> 2) > 16) continue;
+      double end = (Q.cdf[i + 1] - Q.cdf[i]) / Q.beta0;
+      for (int64_t j = i + 1; j < Q.l; ++j) end *= 1.0 - Q.P[j];
       for (int64_t e = rb; e < re; ++e) {
         if (inS(g->col[e])) continue;
         const uint32_t t = oi::coin_threshold(g->p[e]);
-        dead *= t == oi::kThrAlways ? 0.0 : 1.0 - (double)t * (1.0 / 4294967296.0);
+        end *= t == oi::kThrAlways ? 0.0 : 1.0 - (double)t * (1.0 / 4294967296.0);
       }
-      Q.p1_dead = dead;
+      frac += end;
     }
+    Q.p1_dead = frac;
   }
   return OI_OK;
 }
@@ -381,6 +389,7 @@ oi_status upload_query(oi_graph* g, HostQuery& Q) {
   Q.dev.beta0 = Q.beta0;
   Q.dev.skip = Q.skip ? 1 : 0;
   Q.dev.nheavy = (int64_t)Q.heavy.size();
+  Q.dev.p1 = Q.p1_dead >= 0.2 ? 1 : 0;
   if (Q.skip) {
     HIP_TRY(Q.d_R.ensure((size_t)Q.l * sizeof(double)));
     HIP_TRY(Q.d_heavy.ensure(std::max<size_t>(Q.heavy.size(), 1) * sizeof(int32_t)));
@@ -681,9 +690,12 @@ oi_status ensure_lt(oi_graph* g) {
 // The sampling model of a launch's queries (never mixed in one launch).
 // The launch's sampling model, and whether the tiny kernel runs with
 // first-level passes: when at least 70% of the launch's samples are expected
-// to end at v_0 of a single-entry table (measured on the 1M-node graph:
-// passes gained 22-25% for seeds at 85-89%, lost 8% at 50%, where the
-// variant's higher register use costs more than the passes save).
+// to end at their first activated node (measured on 1M-node graph seeds,
+// identical results: single-entry tables at 85-89% gained 20-25% and lost
+// 6% at 50%, where the variant's higher register use costs more than the
+// passes save; tables of 3-10 entries at 71-96% gained 7-71% and lost 3% at
+// 73%).  Single-entry launches get the instantiation whose passes take only
+// such tables: the general one runs them 5-10% slower.
 oi_status set_model(const oi_graph* g, oi::SampleLaunch& A, const std::vector<const HostQuery*>& qs,
                     const std::vector<SegReq>& segs) {
   A.mc = qs.empty() ? 0 : qs[0]->dev.mc;
@@ -691,12 +703,19 @@ oi_status set_model(const oi_graph* g, oi::SampleLaunch& A, const std::vector<co
   for (const HostQuery* q : qs)
     if (q->dev.mc != A.mc || q->dev.lt != A.lt) return fail(OI_ESTATE, "a launch mixes sampling models");
   A.lt_iv = g->d_lt.as<oi::LtEdge>();
-  double ending = 0.0, total = 0.0;
+  double ending = 0.0, ending1 = 0.0, total = 0.0;
   for (const SegReq& r : segs) {
     ending += (double)r.count * qs[r.q]->p1_dead;
+    if (qs[r.q]->l == 1) ending1 += (double)r.count * qs[r.q]->p1_dead;
     total += (double)r.count;
   }
-  A.p1 = (!A.mc && !A.lt && total > 0.0 && ending >= 0.7 * total) ? 1 : 0;
+  A.p1 = 0;
+  if (!A.mc && !A.lt && total > 0.0) {
+    if (ending1 >= 0.7 * total)
+      A.p1 = 1;  // the leaner instantiation: its passes take single-entry tables only
+    else if (ending >= 0.7 * total)
+      A.p1 = 2;
+  }
   return OI_OK;
 }
 
@@ -1775,6 +1794,7 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
     qd.skipR = d_R;
     qd.heavy = d_heavy;
     qd.nheavy = (int64_t)Q.heavy.size();
+    qd.p1 = Q.p1_dead >= 0.2 ? 1 : 0;
     hipStream_t st = g->stream;
     oi_status status = OI_OK;
     // every exit below waits for the stream first: the copies read host
@@ -1819,7 +1839,7 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
         A.nbig = nullptr;
         A.soft_cap = (uint32_t)qcap;
         A.soft_budget = 0;
-        A.p1 = Q.p1_dead >= 0.7 ? 1 : 0;
+        A.p1 = Q.p1_dead >= 0.7 ? (Q.l == 1 ? 1 : 2) : 0;
         OI_TRY(launch_tiers(g, A, false, nullptr, st, blocks));
         unsigned long long h[18] = {0};
         HIP_TRY(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));

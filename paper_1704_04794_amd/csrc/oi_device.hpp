@@ -65,6 +65,9 @@ struct QueryDev {
   const double* skipR;   // l values (skip only)
   const int32_t* heavy;  // nheavy table indices, ascending (skip only)
   int64_t nheavy;
+  // 1: the tiny kernel's first-level passes are worth running for this query
+  // (tables of at most 16 entries; a decision of speed, not of results)
+  int32_t p1;
 };
 
 // LT model: edge e is live iff lo <= W_v <= last for its target v's choice
@@ -163,9 +166,10 @@ struct SampleLaunch {
   // large kernel runs an instantiation of its own
   int32_t lt;
   const LtEdge* lt_iv;             // per edge (LT launches)
-  // 1: the tiny kernel runs its instantiation with first-level passes (chosen
-  // on the host when most of the launch's samples belong to single-entry
-  // Stage-1 tables whose v_0 often activates nothing)
+  // the tiny kernel's instantiation (chosen on the host from how often the
+  // launch's samples are expected to end at their first activated node): 0
+  // without first-level passes, 1 with passes over single-entry Stage-1
+  // tables, 2 with passes over tables of up to 16 entries
   int32_t p1;
 };
 

@@ -320,3 +320,54 @@ def test_single_entry_tables_bit_exact(P):
         assert a[f] == b["rsa"][f], (f, a[f], b["rsa"][f])
     assert a["oi"] == b["oi"]
     G.close()
+
+
+def test_multi_entry_first_level_bit_exact(P):
+    """Seed sets with Stage-1 tables of 2..16 entries whose samples mostly end
+    at their first activated node (low probabilities), so that the tiny
+    kernel runs its first-level passes over them: the selection, the later
+    entries' coins and the selected node's out-edge coins are taken in the
+    pass, everything else in the cascade.  Entries whose rows span more than
+    sixteen groups, edges back into S, p = 1 edges, a 17-entry table (beyond
+    the passes) and several seeds.  Y and E bit-exact against the oracle."""
+    rng = np.random.default_rng(23)
+    n = 2000
+    edges = {}
+    low = lambda: float(rng.choice([0.002, 0.01, 0.05, 1.0], p=[0.5, 0.35, 0.149, 0.001]))
+    # seed u in 0..9 has k_u out-neighbours among 20..59 (table entries)
+    sizes = [2, 3, 4, 5, 7, 8, 11, 16, 17, 6]
+    for u, k in enumerate(sizes):
+        for t in rng.choice(np.arange(20, 60), size=k, replace=False):
+            edges[(u, int(t))] = float(rng.choice([0.003, 0.01, 0.05]))
+    # rows of the entries: mostly short, a few longer than sixteen groups,
+    # some edges back to the seeds
+    for v in range(20, 60):
+        d = 80 if v % 13 == 0 else int(rng.integers(0, 8))
+        for t in rng.choice(np.arange(60, n), size=d, replace=False):
+            edges[(v, int(t))] = low()
+        if v % 5 == 0:
+            edges[(v, int(v % 10))] = 0.5
+    for u in range(60, n):
+        for t in rng.choice(n, size=4, replace=False):
+            if t != u:
+                edges[(u, int(t))] = low()
+    src = np.array([a for a, _ in edges])
+    dst = np.array([b for _, b in edges])
+    p = np.array(list(edges.values()), np.float32)
+    g = graph_from_edges(n, src, dst, p)
+    G = _gpu_graph(P, g)
+    sets = [[u] for u in range(10)] + [[0, 1], [2, 3, 4]]
+    for qid, S in enumerate(sets):
+        tab = O.stage1(g, S)
+        _compare(P, g, S, 40_000, qid=qid, G=G, label=f"multi-entry S={S} l={tab['l']}")
+        _compare(P, g, S, 20_000, qid=qid, stream=1, first=555_555_555, G=G, label=f"multi-entry S={S} X'")
+    # every set in one batched estimate (one launch per round over all of
+    # them), replayed by the oracle set by set
+    qids = np.arange(40, 40 + len(sets), dtype=np.uint32)
+    batch = G.estimate_batch([np.array(S, np.int32) for S in sets], 0.2, 0.1, query_ids=qids)
+    for S, q, a in zip(sets, qids, batch):
+        b = O.estimate(g, S, 0.2, 0.1, 0, int(q), RUN_SEED)
+        for f in ("T1", "h1", "nsigma", "D", "T", "hT"):
+            assert a[f] == b["rsa"][f], (S, f, a[f], b["rsa"][f])
+        assert a["oi"] == b["oi"], S
+    G.close()
