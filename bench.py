@@ -25,6 +25,10 @@ query.
         |S| = 1, 10, 100, a SIEA estimate, the queue-cap comparison and the
         backward over all edges; with --c5-sets, SOIEA estimates at the
         workload's eps = 0.05, delta = 1e-6 for K sets of each size
+    python bench.py --workload skip-density
+        Stage-1 skip sampling against one coin per entry on a 1,000-seed
+        table of the 1M-node graph under edge models from dense to sparse,
+        and which of the two the default density test picks
 """
 from __future__ import annotations
 
@@ -447,26 +451,56 @@ def batched_vs_single_small(P, args):
             "rounds_per_estimate": sum(r["rounds"] for r in single) / q}
 
 
-def stage1_skip_gain(P, G, g, label, S, N, qid=0):
-    """Fixed-count IICP throughput of one long-table seed set with Stage-1 skip
-    sampling (the default for tables of >= 4096 entries) and with one coin per
-    table entry (skip sampling off): same law, different samples."""
+def stage1_skip_gain(P, g, S, models, N, qid=99, repeats=1):
+    """Stage-1 skip sampling against one coin per table entry, on the long
+    Stage-1 table of one seed set under several edge models: fixed-count
+    IICP time (best of `repeats` after a warm run) with skip sampling forced
+    (density test off), with plain coins (skip sampling off), and at the
+    default settings, whose choice is named by which of the two it
+    reproduces (same law, different samples).  The table's light mass per
+    256-entry segment and the walks' and coins' draw counts come from the
+    library's own table."""
+    import numpy as np
     import torch
-    out = {"workload": label, "k": int(len(S)), "samples": N}
-    for name, min_l in (("plain", 1 << 62), ("skip", 4096)):
-        P.oi_set_stage1_skip(G.h, min_l)
-        G.sample_fixed(S, N, query_id=qid)  # warm
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, _, r = G.sample_fixed(S, N, query_id=qid)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t
-        out["l"] = r["l"]
-        out[name] = {"seconds": dt, "samples_per_s": N / dt, "mean_y": r["sum_y"] / N}
-    P.oi_set_stage1_skip(G.h, 4096)
-    out["speedup"] = out["plain"]["seconds"] / out["skip"]["seconds"]
-    log(f"stage-1 skip sampling, {label}: {out}")
-    return out
+
+    from oi_inputs import Graph as InputGraph
+    rows = []
+    for label, p in models:
+        gg = g if p is None else InputGraph(g.n, g.row_ptr, g.col, p)
+        G = P.Graph.from_inputs(gg)
+        t = P.oi_stage1_table(G.h, S)
+        Pj = t["P"]
+        light = (Pj > 0.0) & (Pj < 0.5)
+        nseg = (t["l"] + 255) // 256
+        row = {"model": label, "samples": N, "l": t["l"], "light_mass_per_segment": float(Pj[light].sum()) / nseg,
+               "walk_draws": nseg + float(Pj[light].sum()), "coin_blocks": t["l"] / 4}
+        for name, min_l, cost in (("plain", 1 << 62, 8.0), ("skip", 4096, 0.0), ("default", 4096, 8.0)):
+            P.oi_set_stage1_skip(G.h, min_l)
+            P.oi_set_stage1_skip_cost(G.h, cost)
+            G.sample_fixed(S, N, query_id=qid)  # warm
+            torch.cuda.synchronize()
+            best, r = None, None
+            for _ in range(repeats):
+                t0 = time.perf_counter()
+                _, _, r = G.sample_fixed(S, N, query_id=qid)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                best = dt if best is None else min(best, dt)
+            row[name] = {"seconds": best, "samples_per_s": N / best, "mean_y": r["sum_y"] / N, "sum_y": r["sum_y"]}
+        row["skip_vs_plain"] = row["plain"]["seconds"] / row["skip"]["seconds"]
+        d = row["default"]["sum_y"]
+        row["default_takes"] = ("skip" if d == row["skip"]["sum_y"] else
+                                "plain" if d == row["plain"]["sum_y"] else "unknown")
+        G.close()
+        log(f"stage-1 skip sampling, {label}: {row}")
+        rows.append(row)
+    return rows
+
+
+def skip_models(g, consts):
+    """The workload's own trivalency p, then constant p for each of `consts`."""
+    import numpy as np
+    return [("trivalency", None)] + [(f"p = {c}", np.full(g.m, c, np.float32)) for c in consts]
 
 
 def seed_spread(P, G, g, eps, delta, count):
@@ -539,10 +573,12 @@ def main():
     ap.add_argument("--variant", type=int, default=-1)
     ap.add_argument("--pipeline", type=int, choices=(0, 1, 2), default=None,
                     help="RSA rounds: 0 read back one at a time, 1 queued (default), 2 queued, one graph each")
-    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m", "er2k", "accuracy"), default="cl1m",
+    ap.add_argument("--workload", choices=("cl1m", "cl4m", "cl100m", "er2k", "accuracy", "skip-density"),
+                    default="cl1m",
                     help="cl1m: the single-query throughput line (default); cl4m: batched vs one-at-a-time; "
                          "cl100m: the billion-edge graph; er2k: batched vs one-at-a-time where one query "
-                         "leaves the GPU idle")
+                         "leaves the GPU idle; skip-density: Stage-1 skip sampling against plain coins over "
+                         "table densities")
     ap.add_argument("--queries", type=int, default=None,
                     help="cl4m: seed sets in the subset (default 32); er2k: seed sets (default 256)")
     ap.add_argument("--no-autotune", action="store_true", help="cl4m: keep the default sampler schedule")
@@ -596,6 +632,15 @@ def main():
         return
     if args.workload == "accuracy":
         print(json.dumps(accuracy_experiment(P, args)), flush=True)
+        return
+    if args.workload == "skip-density":
+        from oi_inputs import top_outdeg_seed_set
+        g, _, _ = make_config("cl1m")
+        out = {"workload": "cl1m graph, 1,000 seeds from the top-1% out-degree nodes, under its trivalency p "
+                           "and constant p from 0.03 down to 0.001; 2^20 fixed-count samples, best of 3",
+               "rows": stage1_skip_gain(P, g, top_outdeg_seed_set(g, 1000, 7),
+                                        skip_models(g, (0.03, 0.01, 0.003, 0.001)), 1 << 20, repeats=3)}
+        print(json.dumps(out), flush=True)
         return
     t = time.perf_counter()
     g, sets, extra = make_config("cl1m")
@@ -683,9 +728,10 @@ def main():
         return
     out["spread"] = seed_spread(P, G, g, eps, delta, args.spread)
     from oi_inputs import top_outdeg_seed_set
-    out["stage1_skip"] = stage1_skip_gain(
-        P, G, g, "cl1m (trivalency p), 1,000 seeds from the top-1% out-degree nodes",
-        top_outdeg_seed_set(g, 1000, 7), 1 << 18, qid=99)
+    out["stage1_skip"] = {
+        "workload": "cl1m graph, 1,000 seeds from the top-1% out-degree nodes: its own trivalency p (a dense "
+                    "table) and constant p = 0.003 (a sparse one)",
+        "rows": stage1_skip_gain(P, g, top_outdeg_seed_set(g, 1000, 7), skip_models(g, (0.003,)), 1 << 18)}
     gr = gather_roofline(G)
     out["roofline"]["measured_gather_gbps"] = gr["gbps"]
     out["roofline"]["frac_of_measured_gather"] = alg_gbps / gr["gbps"] if gr["gbps"] > 0 else None

@@ -296,8 +296,9 @@ oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
 oi_status oi_set_pipeline(oi_graph* g, int mode);
 /* Stage-1 skip sampling (part of the sampling specification; results depend
  * on it).  A Stage-1 table of l >= max(min_l, 65) entries (default min_l =
- * 4096) is sampled after the selection i (Alg. 1, Stage 1) without one coin
- * per entry: entries with P_j >= 1/2 keep their coins (kind 2); entries with
+ * 4096) that passes the density test of oi_set_stage1_skip_cost is sampled
+ * after the selection i (Alg. 1, Stage 1) without one coin per entry:
+ * entries with P_j >= 1/2 keep their coins (kind 2); entries with
  * 0 < P_j < 1/2 are found by one walk per segment of 256 table indices.  In
  * segment m (indices [256m, 256m + 256)) R_j is the product of (1 - P_k) over
  * its entries k <= j with 0 < P_k < 1/2 (fp64, ascending k).  A walk stands
@@ -311,6 +312,17 @@ oi_status oi_set_pipeline(oi_graph* g, int mode);
  * examined-edge count still includes the l - 1 - i entries after i.
  * Applies to calls made after it; min_l < 1 gives OI_EINVAL. */
 oi_status oi_set_stage1_skip(oi_graph* g, int64_t min_l);
+/* The density test of Stage-1 skip sampling (part of the sampling
+ * specification).  A walk step (a Philox draw whose counter is the walk's
+ * last position, then a search) costs several coin blocks, so a long table is
+ * skip-sampled only when W * cost <= l / 4, where W = ceil(l / 256) plus the
+ * sum of P_j over its entries with 0 < P_j < 1/2 (fp64, the count first,
+ * then ascending j) is the walks' expected number of draws from i = 0 and
+ * l / 4 the number of coin blocks.  Default cost 8 (one walk step measured
+ * at about 6.5 coin blocks on the 1M-node graph); cost 0 drops the test.
+ * Applies to calls made after it; a negative or non-finite cost gives
+ * OI_EINVAL. */
+oi_status oi_set_stage1_skip_cost(oi_graph* g, double cost);
 
 /* What oi_autotune chose and measured. */
 typedef struct {

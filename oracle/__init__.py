@@ -54,6 +54,8 @@ def lib():
         L.oo_philox.restype = None
         L.oo_set_stage1_skip.argtypes = [i64]
         L.oo_set_stage1_skip.restype = None
+        L.oo_set_stage1_skip_cost.argtypes = [C.c_double]
+        L.oo_set_stage1_skip_cost.restype = None
         g = [i64, i64, vp, vp, vp]
         L.oo_sample_fixed.argtypes = g + [vp, i64, u32, u32, u32, u64, u64, vp, vp, vp, vp, C.c_int]
         L.oo_stage1.argtypes = g + [vp, i64, i64, _P(i64), _P(dbl), vp, vp, vp, vp, _P(i64)]
@@ -125,8 +127,16 @@ def philox(ctr, key):
 
 def set_stage1_skip(min_l: int):
     """Tables of at least max(min_l, 65) entries use Stage-1 skip sampling
-    (the default min_l is 4096); a process-wide setting of the oracle."""
+    (the default min_l is 4096) when they pass its density test; a
+    process-wide setting of the oracle."""
     lib().oo_set_stage1_skip(int(min_l))
+
+
+def set_stage1_skip_cost(cost: float):
+    """Draw-cost ratio of skip sampling's density test (default 8): a long
+    table is skip-sampled iff W * cost <= l / 4, W = ceil(l / 256) + the sum
+    of its light entries' P_j; 0 drops the test.  Process-wide."""
+    lib().oo_set_stage1_skip_cost(float(cost))
 
 
 def stage1(g, seeds, cap: int = 1 << 24):

@@ -69,8 +69,14 @@
  *       interval.  An LT sample is the set reachable from S over live edges;
  *       SIEA_LT runs RSA on its size X = |S| + Y over [a, b] = [|S|, n].
  *   R16 Stage-1 skip sampling (a different consumption of randomness for the
- *       same law, used when l >= max(skip_min_l, 65); skip_min_l = 4096 unless
- *       set): after the selection i, entries with P_j >= 1/2 ("heavy") are
+ *       same law, used when l >= max(skip_min_l, 65), skip_min_l = 4096
+ *       unless set, and the table is sparse enough for the walks to pay:
+ *       W * skip_cost <= l / 4, where W = ceil(l / 256) plus the sum of P_j
+ *       over the light entries (fp64, the count first, then ascending j) is
+ *       the walks' expected number of draws from i = 0, l / 4 the coins'
+ *       Philox blocks, and skip_cost = 8 unless set (0: no density test), the
+ *       measured cost of one walk step in coin blocks rounded up to a power
+ *       of two): after the selection i, entries with P_j >= 1/2 ("heavy") are
  *       flipped with their own coins as in R4; entries with 0 < P_j < 1/2
  *       ("light") are visited by one walk per segment of 256 table indices.
  *       Within segment m (indices [256m, 256m + 256)) R_j is the product of
@@ -96,10 +102,13 @@ typedef unsigned __int128 oo_u128;
 enum { OO_OK = 0, OO_EINVAL = -1, OO_ERANGE = -2, OO_ENOMEM = -3 };
 enum { KIND_EDGE = 0, KIND_SELECT = 1, KIND_STAGE1 = 2, KIND_SKIP = 3, KIND_LT = 4 };
 
-/* R16: the spec's constants and the table size from which skip sampling is used */
+/* R16: the spec's constants, the table size from which skip sampling is
+ * used, and the draw-cost ratio of its density test */
 enum { SKIP_SEG = 256, SKIP_LMIN_FLOOR = 65 };
 static int64_t g_skip_min_l = 4096;
+static double g_skip_cost = 8.0;
 void oo_set_stage1_skip(int64_t min_l) { g_skip_min_l = min_l; }
+void oo_set_stage1_skip_cost(double cost) { g_skip_cost = cost; }
 
 /* ------------------------------------------------------------------------ */
 /* Philox4x32-10, from the published description (multiply-xor rounds with  */
@@ -273,6 +282,13 @@ int oo_table_build(const oo_graph *g, const int32_t *seeds, int64_t k, oo_table 
     t->beta0 = t->cdf[l];
     /* R16 */
     t->skip = l >= (g_skip_min_l > SKIP_LMIN_FLOOR ? g_skip_min_l : SKIP_LMIN_FLOOR);
+    if (t->skip && g_skip_cost > 0.0) {
+        /* the walks' expected draws against the coins' blocks */
+        double W = (double)((l + SKIP_SEG - 1) / SKIP_SEG);
+        for (j = 0; j < l; ++j)
+            if (t->P[j] > 0.0 && t->P[j] < 0.5) W = W + t->P[j];
+        t->skip = W * g_skip_cost <= (double)l / 4.0;
+    }
     if (t->skip) {
         t->R = malloc(sizeof(double) * (size_t)l);
         t->heavy = malloc(sizeof(int64_t) * (size_t)l);

@@ -99,6 +99,7 @@ def _load():
         "oi_set_routing": [vp, ci, i64],
         "oi_set_pipeline": [vp, ci],
         "oi_set_stage1_skip": [vp, i64],
+        "oi_set_stage1_skip_cost": [vp, C.c_double],
         "oi_autotune": [vp, i32, vp, vp, vp, u64, u32, P(oi_autotune_result)],
     }
     for name, args in sig.items():
@@ -285,8 +286,14 @@ def oi_set_routing(g, small_direct=-1, large_qcap=-1):
 
 
 def oi_set_stage1_skip(g, min_l):
-    """Stage-1 tables of at least max(min_l, 65) entries use skip sampling."""
+    """Stage-1 tables of at least max(min_l, 65) entries that pass the density
+    test use skip sampling."""
     _check("oi_set_stage1_skip", _lib.oi_set_stage1_skip(g, int(min_l)))
+
+
+def oi_set_stage1_skip_cost(g, cost):
+    """Draw-cost ratio of skip sampling's density test (default 8; 0: none)."""
+    _check("oi_set_stage1_skip_cost", _lib.oi_set_stage1_skip_cost(g, float(cost)))
 
 
 def oi_set_pipeline(g, mode):

@@ -217,9 +217,11 @@ struct oi_graph {
   bool soft_bwd = false;            // the backward may send samples above the soft cap to the full-queue pass
   int variant = 0;
   bool use_tiny = true;
-  // Stage-1 tables of at least max(skip_min_l, 65) entries are sampled by
-  // skip sampling (part of the sampling specification, see oi_set_stage1_skip)
+  // Stage-1 tables of at least max(skip_min_l, 65) entries that pass the
+  // density test with draw-cost ratio skip_cost are sampled by skip sampling
+  // (part of the sampling specification, see oi_set_stage1_skip)
   int64_t skip_min_l = 4096;
+  double skip_cost = 8.0;
   uint32_t chunk = 256;
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
   // samples per sampling launch (set at creation from free memory, at most
@@ -312,10 +314,19 @@ oi_status build_table(const oi_graph* g, const int32_t* seeds, int64_t k, HostQu
     rest = rest * (1.0 - Q.P[j]);
   }
   Q.beta0 = Q.cdf[Q.l];
-  // Stage-1 skip sampling for long tables: heavy entries (P >= 1/2) keep
-  // their coins; light ones (0 < P < 1/2) are found by walks over the
-  // products of (1 - P) within segments of kSkipSeg entries
+  // Stage-1 skip sampling for long sparse tables: heavy entries (P >= 1/2)
+  // keep their coins; light ones (0 < P < 1/2) are found by walks over the
+  // products of (1 - P) within segments of kSkipSeg entries.  A table is
+  // sparse enough when the walks' expected draws (one per segment plus one
+  // per live light entry) times skip_cost are at most the coins' l / 4
+  // Philox blocks
   Q.skip = Q.l >= std::max<int64_t>(g->skip_min_l, oi::kSkipMinFloor);
+  if (Q.skip && g->skip_cost > 0.0) {
+    double W = (double)((Q.l + oi::kSkipSeg - 1) / oi::kSkipSeg);
+    for (int64_t j = 0; j < Q.l; ++j)
+      if (Q.P[j] > 0.0 && Q.P[j] < 0.5) W = W + Q.P[j];
+    Q.skip = W * g->skip_cost <= (double)Q.l / 4.0;
+  }
   Q.R.clear();
   Q.heavy.clear();
   if (Q.skip) {
@@ -2141,6 +2152,13 @@ oi_status oi_set_stage1_skip(oi_graph* g, int64_t min_l) {
   if (!g) return fail(OI_EINVAL, "null graph");
   if (min_l < 1) return fail(OI_EINVAL, "min_l must be positive");
   g->skip_min_l = min_l;
+  return OI_OK;
+}
+
+oi_status oi_set_stage1_skip_cost(oi_graph* g, double cost) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (!(cost >= 0.0) || cost > 1e300) return fail(OI_EINVAL, "cost must be finite and non-negative");
+  g->skip_cost = cost;
   return OI_OK;
 }
 

@@ -17,6 +17,7 @@ typedef struct {
 } rsa_result;
 
 void oo_set_stage1_skip(int64_t min_l);
+void oo_set_stage1_skip_cost(double cost);
 void oo_philox(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 int oo_sample_fixed(int64_t, int64_t, const int64_t *, const int32_t *, const float *, const int32_t *, int64_t,
                     uint32_t, uint32_t, uint32_t, uint64_t, uint64_t, uint32_t *, uint64_t *, uint64_t *, double *,
@@ -105,6 +106,7 @@ int main(void)
 
     for (int skip = 0; skip < 2; ++skip) {
         oo_set_stage1_skip(skip ? 1 : 4096);
+        oo_set_stage1_skip_cost(skip ? 0.0 : 8.0);
         CHECK(oo_sample_fixed(n, m, rp, col, p, seeds, 5, 1, 9, 0, 0, 4096, y, e, sums, &beta0, 3) == 0);
         CHECK(oo_sample_fixed(n, m, rp, col, p, seeds, 1, 1, 9, 1, 1u << 30, 512, y, NULL, sums, &beta0, 1) == 0);
         CHECK(oo_estimate(n, m, rp, col, p, seeds, 5, 0.2, 0.1, 0, 3, 9, &oi, &is, &beta0, &k, &r) == 0);
@@ -117,6 +119,7 @@ int main(void)
         free(acc2);
     }
     oo_set_stage1_skip(4096);
+    oo_set_stage1_skip_cost(8.0);
     CHECK(oo_mc_fixed(n, m, rp, col, p, seeds, 5, 1, 9, 0, 0, 2048, y, e, sums, &k, 2) == 0);
     int64_t sel[64];
     CHECK(oo_selection(n, m, rp, col, p, seeds, 5, 1, 9, 0, 0, 64, sel) == 0);

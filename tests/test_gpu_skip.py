@@ -1,9 +1,11 @@
 """GPU parity of Stage-1 skip sampling (long Stage-1 tables; the
 specification in include/oi.h, oi_set_stage1_skip) with the oracle: per-sample
 Y and E bit for bit, the backward per edge, and an RSA estimate, with the
-threshold lowered so that tables of a few hundred entries use it (the
-workloads' long tables use it at the default threshold and are covered by
-the 4M-node tests)."""
+threshold lowered and the density test off so that tables of a few hundred
+dense entries use it; and the density test's decision at the default
+settings, taken alike on both sides (the configured workloads' long tables
+are dense and keep their plain coins; they are covered by the 4M-node
+tests)."""
 import numpy as np
 import pytest
 
@@ -25,13 +27,16 @@ def P():
 @pytest.fixture
 def skip65():
     O.set_stage1_skip(65)
+    O.set_stage1_skip_cost(0)
     yield 65
     O.set_stage1_skip(4096)
+    O.set_stage1_skip_cost(8)
 
 
 def _graph(P, g, min_l):
     G = P.Graph.from_inputs(g)
     P.oi_set_stage1_skip(G.h, min_l)
+    P.oi_set_stage1_skip_cost(G.h, 0)
     return G
 
 
@@ -108,3 +113,18 @@ def test_skip_noalloc_matches(P, skip65):
     y2, _, r2 = G.sample_fixed([0], N, query_id=7)
     assert torch.equal(y1, y2) and r1["sum_y"] == r2["sum_y"]
     G.close()
+
+
+@pytest.mark.parametrize("p", [0.027, 0.0275])
+def test_density_test_agrees_with_the_oracle(P, p):
+    """Stars of 4096 leaves with every P_j = p, at the default settings
+    (tables from 4096 entries, cost 8): the density test skip-samples the
+    first (8 W = 8 (16 + 4096 p) = 1013 <= 1024) and not the second (1029);
+    both sides take the same decision, so the samples agree bit for bit."""
+    g = star_graph(np.full(4096, p, np.float32))
+    G = P.Graph.from_inputs(g)
+    try:
+        r, _ = _compare(G, g, [0], 1 << 14, qid=11, label=f"density test p={p}")
+        assert r["l"] == 4096
+    finally:
+        G.close()

@@ -28,8 +28,10 @@ SEED = 0x17044794
 @pytest.fixture
 def skip_from_65():
     O.set_stage1_skip(65)
+    O.set_stage1_skip_cost(0)    # no density test: the tables here are dense
     yield
     O.set_stage1_skip(4096)
+    O.set_stage1_skip_cost(8)
 
 
 def _star_probs(l, rng):
@@ -134,3 +136,44 @@ def test_skip_backward_star_gradient_is_one(skip_from_65):
     est = b0 * r["acc"] / N
     se = np.sqrt(np.maximum(b0 * b0 * r["acc2"] / N - est * est, 0.0) / N)
     assert np.all(np.abs(est - 1.0) < 5 * se + 1e-9)
+
+
+def _walk_draws(P):
+    """W of the density test in the order the specification fixes: the
+    segment count, then the light entries' P_j in ascending j."""
+    W = float((len(P) + 255) // 256)
+    for x in P:
+        x = float(x)
+        if 0.0 < x < 0.5:
+            W = W + x
+    return W
+
+
+@pytest.mark.parametrize("p, skipped", [(0.002, True), (0.027, True), (0.0275, False), (0.2, False)])
+def test_density_test_decides_by_the_expected_draws(p, skipped):
+    """A star of 4096 leaves with every P_j = p: W = 16 + 4096 p walk draws
+    against 1024 coin blocks, so with the default cost 8 the table is
+    skip-sampled iff p <= 0.02734375.  Its samples are then those drawn with
+    the density test off (cost 0), else those of the plain coins (skip
+    sampling off); the two differ."""
+    g = star_graph(np.full(4096, p, np.float32))
+    t = O.stage1(g, [0])
+    assert t["l"] == 4096
+    W = _walk_draws(t["P"])
+    assert abs(W - (16 + 4096 * p)) < 1e-3 * W
+    assert (W * 8.0 <= 4096 / 4.0) == skipped
+    N = 4000
+    d = O.sample_fixed(g, [0], 5, SEED, 0, 0, N, want_e=True)
+    O.set_stage1_skip_cost(0)
+    try:
+        s = O.sample_fixed(g, [0], 5, SEED, 0, 0, N, want_e=True)
+    finally:
+        O.set_stage1_skip_cost(8)
+    O.set_stage1_skip(1 << 40)
+    try:
+        c = O.sample_fixed(g, [0], 5, SEED, 0, 0, N, want_e=True)
+    finally:
+        O.set_stage1_skip(4096)
+    assert not np.array_equal(s["y"], c["y"])
+    np.testing.assert_array_equal(d["y"], (s if skipped else c)["y"])
+    np.testing.assert_array_equal(d["e"], (s if skipped else c)["e"])
