@@ -302,11 +302,13 @@ struct NoFirstLevel {};
 // separate instantiation so that the IICP loop carries none of their
 // bookkeeping.  PASS: the forward IICP instantiation with first-level passes,
 // over single-entry tables only (1) or over tables of up to P1L_MAXL entries (2).
-// Each instantiation is given the occupancy it is held to (the pass variant
-// needs more registers; the others keep six waves per SIMD, the forward at
-// the price of a few spilled values).
+// Each instantiation is given the occupancy it is held to: five waves per
+// SIMD for the single-entry pass variant and four for the general one (they
+// need more registers; the former spills ten values for its fifth wave), six
+// for the forward without passes (a few spilled values), five for the
+// backward.
 template <int CAP, bool BWD, bool MC, int PASS>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS ? 4 : (BWD ? 5 : 6)))) tiny_kernel(SampleLaunch A) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS == 1 ? 5 : (PASS ? 4 : (BWD ? 5 : 6))))) tiny_kernel(SampleLaunch A) {
   __shared__ int32_t vis_all[4][CAP * 64];
   // the current segment's CDF and table nodes (tables of 2..TINY_LMAX
   // entries): the samples a wave starts in an iteration all come from that
