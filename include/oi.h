@@ -282,6 +282,19 @@ oi_status oi_set_tuning(oi_graph* g, int variant, int chunk, int tiny, int tiny_
  * large_qcap reallocates the pool.  Results do not depend on either
  * setting.  Errors: OI_EINVAL for a null graph or small_direct > 2. */
 oi_status oi_set_routing(oi_graph* g, int small_direct, int64_t large_qcap);
+/* First-level passes of the one-sample-per-lane kernel (a tuning and testing
+ * aid; results never depend on it).  In a pass the kernel tests 64 new
+ * samples of a segment at once for whether they end at their first
+ * activated node (Alg. 1: no later Stage-1 entry and no out-edge of that
+ * node into a node outside S live) and finishes those; the rest run the
+ * cascade.  mode -1 (default): per launch, the instantiation with passes
+ * over single-entry tables when at least 70% of the launch's samples are
+ * expected to end so in them, else the one with passes over tables of up to
+ * 16 entries when 70% do in all, else none; in either, only tables where
+ * at least 20% are expected to end so take passes.  0: no passes.  1 / 2:
+ * that instantiation for every launch, and passes for every table it
+ * takes.  Applies to calls made after it; another mode gives OI_EINVAL. */
+oi_status oi_set_first_level(oi_graph* g, int mode);
 /* Queued RSA rounds.  In steps 2 and 3 of the RSA estimator (Alg. 3) the
  * number of samples is fixed when the step starts, so a round that neither
  * starts nor ends a step determines the next one.  mode 1 (the default):

@@ -13,7 +13,7 @@ from ._binding import (  # noqa: F401
     oi_coin_probe, oi_gather_probe,
     oi_estimate, oi_estimate_batch, oi_graph_create, oi_graph_destroy, oi_graph_get_probs, oi_graph_set_probs,
     oi_graph_set_theta, oi_last_error,
-    oi_num_variants, oi_sample_fixed, oi_sample_fixed_noalloc, oi_sample_lt, oi_sample_mc, oi_set_pipeline, oi_set_routing, oi_set_stage1_skip, oi_set_stage1_skip_cost, oi_set_stream, oi_set_tuning, oi_stage1_table,
+    oi_num_variants, oi_sample_fixed, oi_set_first_level, oi_sample_fixed_noalloc, oi_sample_lt, oi_sample_mc, oi_set_pipeline, oi_set_routing, oi_set_stage1_skip, oi_set_stage1_skip_cost, oi_set_stream, oi_set_tuning, oi_stage1_table,
     oi_timing_enable, oi_timing_get, oi_variant_info)
 
 RUN_SEED = 0x17044794

@@ -100,6 +100,7 @@ def _load():
         "oi_set_pipeline": [vp, ci],
         "oi_set_stage1_skip": [vp, i64],
         "oi_set_stage1_skip_cost": [vp, C.c_double],
+        "oi_set_first_level": [vp, C.c_int],
         "oi_autotune": [vp, i32, vp, vp, vp, u64, u32, P(oi_autotune_result)],
     }
     for name, args in sig.items():
@@ -294,6 +295,11 @@ def oi_set_stage1_skip(g, min_l):
 def oi_set_stage1_skip_cost(g, cost):
     """Draw-cost ratio of skip sampling's density test (default 8; 0: none)."""
     _check("oi_set_stage1_skip_cost", _lib.oi_set_stage1_skip_cost(g, float(cost)))
+
+
+def oi_set_first_level(g, mode):
+    """Tiny kernel's first-level passes: -1 automatic, 0 none, 1 / 2 that instantiation always."""
+    _check("oi_set_first_level", _lib.oi_set_first_level(g, int(mode)))
 
 
 def oi_set_pipeline(g, mode):

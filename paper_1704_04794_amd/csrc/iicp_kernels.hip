@@ -270,6 +270,7 @@ constexpr uint32_t TINY_LMAX = 64;  // longest Stage-1 table the tiny kernel tak
 constexpr uint32_t P1_MAXG = 16;    // first-level passes: v_0's row spans at most this many edge groups
 constexpr uint32_t P1_PEND = 256;   // first-level passes: pending samples per wave (a power of two)
 constexpr uint32_t P1L_MAXL = 16;   // first-level passes: longest Stage-1 table they take
+constexpr uint32_t P1_DIRG = 8;     // single-entry passes hand their coins on for rows of at most this many groups
 enum : uint32_t { T_IDLE = 0, T_START = 1, T_STAGE1 = 2, T_EXPAND = 3, T_POP = 4 };
 
 // Append the flat indices of the lanes with `pred` to a hand-over list.
@@ -357,8 +358,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
   // Everything here is wave-uniform.
   constexpr bool P1 = PASS != 0 && !BWD && !MC;
   constexpr bool P1GEN = P1 && PASS == 2;  // passes also over tables of several entries
+  constexpr bool P1DIR = P1 && PASS == 1;  // pending samples start from their pass's live out-edges of v_0
   __shared__ uint32_t p1thr_all[4][P1 ? 4 * P1_MAXG : 1];
   __shared__ uint32_t pend_all[4][P1 ? P1_PEND : 1];
+  // single-entry tables with v_0's row within P1_DIRG groups: the targets of
+  // v_0's counted slots, and for each pending sample its live counted slots
+  // (its cascade then starts from them instead of drawing v_0's coins again)
+  __shared__ int32_t p1tgt_all[4][P1DIR ? 4 * P1_DIRG : 1];
+  __shared__ uint32_t pmask_all[4][P1DIR ? P1_PEND : 1];
   // tables of 2..P1L_MAXL entries: each entry's Stage-1 coin threshold and
   // its node's row bounds
   __shared__ uint64_t p1sthr_all[4][P1GEN ? P1L_MAXL : 1];
@@ -366,6 +373,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
   __shared__ uint32_t p1re_all[4][P1GEN ? P1L_MAXL : 1];
   uint32_t* wp1thr = p1thr_all[threadIdx.x >> 6];
   uint32_t* wpend = pend_all[threadIdx.x >> 6];
+  int32_t* wp1tgt = p1tgt_all[threadIdx.x >> 6];
+  uint32_t* wpmask = pmask_all[threadIdx.x >> 6];
+  uint32_t pmask = 0;  // a pending sample's live counted slots of v_0 (0: none handed on)
   uint64_t* wsthr = p1sthr_all[threadIdx.x >> 6];
   uint32_t* wrb = p1rb_all[threadIdx.x >> 6];
   uint32_t* wre = p1re_all[threadIdx.x >> 6];
@@ -496,14 +506,16 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
                 // at v_0
                 bool counted = false;
                 uint32_t thr = 0;
+                int32_t tgt = -1;
                 const int64_t e = 4 * (c_rb0 >> 2) + lane;
                 if (lane < 4 * ng && e >= c_rb0 && e < c_re0) {
                   const OI_GLOBAL EdgeGroup* grp = gptr(A.eg) + (e >> 2);
-                  const int32_t tgt = grp->v[e & 3];
+                  tgt = grp->v[e & 3];
                   thr = grp->thr[e & 3];
                   counted = !in_seed_fields(c_k, c_s0, c_smask, c_shash, tgt);
                 }
                 wp1thr[lane] = thr;
+                if (P1DIR && lane < 4 * P1_DIRG) wp1tgt[lane] = tgt;
                 pw.on = Qp->p1 != 0;
                 pw.ng = (uint32_t)ng;
                 pw.g0 = (uint32_t)(c_rb0 >> 2);
@@ -530,6 +542,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
             asm volatile("" : "+s"(pseed));
             bool need = false;           // the sample needs the cascade
             unsigned long long eo = 0;   // its E if it ends at its first node
+            uint32_t lm = 0;             // its live counted slots (rows within P1_DIRG groups)
             if (!P1GEN || !pw.gen) {
   #pragma unroll 1
               for (uint32_t gi = 0; gi < pw.ng; ++gi) {
@@ -537,9 +550,13 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
   #pragma unroll
                 for (int b = 0; b < 4; ++b) {
                   const uint32_t slot = 4 * gi + (uint32_t)b;
-                  if ((pw.mask >> slot) & 1ull) need |= edge_live(d.w[b], wp1thr[slot]);
+                  if (((pw.mask >> slot) & 1ull) && edge_live(d.w[b], wp1thr[slot])) {
+                    need = true;
+                    if (P1DIR && slot < 32u) lm |= 1u << slot;
+                  }
                 }
               }
+              if (pw.ng > P1_DIRG) lm = 0;
               eo = pw.deg;
             } else if constexpr (P1GEN) {
               // Alg. 1 for a table of several entries: the selection i (as the
@@ -597,7 +614,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
               pw.e += uniform64(wave_sum64(done ? eo : 0ull));
             else
               pw.e += (unsigned long long)__popcll(dm) * pw.deg;
-            if (more) wpend[(pw.tail + lane_prefix(mm)) & (P1_PEND - 1)] = (uint32_t)off;
+            if (more) {
+              const uint32_t slot = (pw.tail + lane_prefix(mm)) & (P1_PEND - 1);
+              wpend[slot] = (uint32_t)off;
+              if (P1DIR) wpmask[slot] = lm;
+            }
             pw.tail += (uint32_t)__popcll(mm);
             wave_sync();
             cur += take;
@@ -609,7 +630,9 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
           const uint32_t take = npend < nidle ? npend : nidle;
           const uint32_t rank = lane_prefix(idle);
           if (st == T_IDLE && rank < take) {
-            f = c_flat0 + wpend[(pw.head + rank) & (P1_PEND - 1)];
+            const uint32_t slot = (pw.head + rank) & (P1_PEND - 1);
+            f = c_flat0 + wpend[slot];
+            if (P1DIR) pmask = wpmask[slot];
             st = T_START;
             started = true;
           }
@@ -621,6 +644,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
           const uint32_t rank = lane_prefix(idle);
           if (st == T_IDLE && rank < take) {
             f = cur + rank;
+            pmask = 0;
             st = T_START;
             started = true;
           }
@@ -748,7 +772,27 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(PASS =
         E = (unsigned long long)(c_re0 - c_rb0);
         if (BWD) atomicAdd(&A.acc_tab[0], (unsigned long long)y);
         if (BWD && c_re0 > c_rb0) atomicAdd(&A.acc_node[c_v0], (unsigned long long)y);
-        if (c_re0 > c_rb0) {
+        if (P1DIR && pmask) {
+          // a pending sample whose pass drew v_0's coins: v_0's live
+          // out-edges into nodes outside S (a non-empty set) are expanded
+          // here, in slot order, as the edge-group steps would have done
+          bool overflow = false;
+          for (uint32_t mk = pmask; mk; mk &= mk - 1u) {
+            const int32_t v = wp1tgt[__builtin_ctz(mk)];
+            bool dup = false;
+            for (uint32_t c = 0; c < cnt; ++c) dup |= vis[64 * c] == v;
+            if (!dup) {
+              if (cnt >= (uint32_t)CAP) {
+                overflow = true;
+              } else {
+                vis[64 * cnt] = v;
+                ++cnt;
+              }
+            }
+          }
+          pass_on = overflow;
+          st = overflow ? T_IDLE : T_POP;
+        } else if (c_re0 > c_rb0) {
           lo_e = (uint32_t)c_rb0;
           hi_e = (uint32_t)c_re0;
           g = (uint32_t)(c_rb0 >> 2);

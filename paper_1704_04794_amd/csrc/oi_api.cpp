@@ -222,6 +222,9 @@ struct oi_graph {
   // (part of the sampling specification, see oi_set_stage1_skip)
   int64_t skip_min_l = 4096;
   double skip_cost = 8.0;
+  // first-level passes of the tiny kernel: -1 the host's choice per launch,
+  // 0 none, 1 / 2 that instantiation for every launch (see oi_set_first_level)
+  int first_level = -1;
   uint32_t chunk = 256;
   uint32_t tiny_chunk = 0;  // 0: about eight chunks per resident wave per launch
   // samples per sampling launch (set at creation from free memory, at most
@@ -400,7 +403,7 @@ oi_status upload_query(oi_graph* g, HostQuery& Q) {
   Q.dev.beta0 = Q.beta0;
   Q.dev.skip = Q.skip ? 1 : 0;
   Q.dev.nheavy = (int64_t)Q.heavy.size();
-  Q.dev.p1 = Q.p1_dead >= 0.2 ? 1 : 0;
+  Q.dev.p1 = (g->first_level > 0 || Q.p1_dead >= 0.2) ? 1 : 0;
   if (Q.skip) {
     HIP_TRY(Q.d_R.ensure((size_t)Q.l * sizeof(double)));
     HIP_TRY(Q.d_heavy.ensure(std::max<size_t>(Q.heavy.size(), 1) * sizeof(int32_t)));
@@ -726,6 +729,7 @@ oi_status set_model(const oi_graph* g, oi::SampleLaunch& A, const std::vector<co
       A.p1 = 1;  // the leaner instantiation: its passes take single-entry tables only
     else if (ending >= 0.7 * total)
       A.p1 = 2;
+    if (g->first_level >= 0) A.p1 = g->first_level;
   }
   return OI_OK;
 }
@@ -1805,7 +1809,7 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
     qd.skipR = d_R;
     qd.heavy = d_heavy;
     qd.nheavy = (int64_t)Q.heavy.size();
-    qd.p1 = Q.p1_dead >= 0.2 ? 1 : 0;
+    qd.p1 = (g->first_level > 0 || Q.p1_dead >= 0.2) ? 1 : 0;
     hipStream_t st = g->stream;
     oi_status status = OI_OK;
     // every exit below waits for the stream first: the copies read host
@@ -1850,7 +1854,7 @@ oi_status oi_sample_fixed_noalloc(oi_graph* g, uint32_t query_id, const int32_t*
         A.nbig = nullptr;
         A.soft_cap = (uint32_t)qcap;
         A.soft_budget = 0;
-        A.p1 = Q.p1_dead >= 0.7 ? (Q.l == 1 ? 1 : 2) : 0;
+        A.p1 = g->first_level >= 0 ? g->first_level : (Q.p1_dead >= 0.7 ? (Q.l == 1 ? 1 : 2) : 0);
         OI_TRY(launch_tiers(g, A, false, nullptr, st, blocks));
         unsigned long long h[18] = {0};
         HIP_TRY(hipMemcpyAsync(h, ctl, sizeof(h), hipMemcpyDeviceToHost, st));
@@ -2159,6 +2163,13 @@ oi_status oi_set_stage1_skip_cost(oi_graph* g, double cost) {
   if (!g) return fail(OI_EINVAL, "null graph");
   if (!(cost >= 0.0) || cost > 1e300) return fail(OI_EINVAL, "cost must be finite and non-negative");
   g->skip_cost = cost;
+  return OI_OK;
+}
+
+oi_status oi_set_first_level(oi_graph* g, int mode) {
+  if (!g) return fail(OI_EINVAL, "null graph");
+  if (mode < -1 || mode > 2) return fail(OI_EINVAL, "first-level mode must be -1, 0, 1 or 2");
+  g->first_level = mode;
   return OI_OK;
 }
 

@@ -68,6 +68,7 @@ int main(void)
     EXPECT(oi_set_pipeline(NULL, 1), OI_EINVAL);
     EXPECT(oi_set_stage1_skip(NULL, 100), OI_EINVAL);
     EXPECT(oi_set_stage1_skip_cost(NULL, 8.0), OI_EINVAL);
+    EXPECT(oi_set_first_level(NULL, 1), OI_EINVAL);
     EXPECT(oi_gather_probe(NULL, 1024, 0, &u64a, &u64b, &d), OI_EINVAL);
     EXPECT(oi_coin_probe(NULL, 1024, 4, 0, 0, &u64a, &d), OI_EINVAL);
     int a, b, c, e;

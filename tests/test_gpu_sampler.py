@@ -278,7 +278,11 @@ def test_single_entry_tables_bit_exact(P):
     cascade only for samples with a live one): v_0's row inside one edge
     group, across two, four and seven groups, longer than sixteen groups,
     empty, with edges back into S, with p = 1 edges, and with several seeds.
-    Y and E bit-exact against the oracle, and the estimate's sums equal."""
+    Every table runs under each first-level mode (the host's choice, none,
+    and each pass instantiation forced), so that pending samples also start
+    from the live out-edges their pass drew, including a v_0 with 20 certain
+    out-edges, which overflows the per-lane list at once.  Y and E bit-exact
+    against the oracle, and the estimate's sums equal."""
     rng = np.random.default_rng(11)
     n = 300
     edges = []  # (src, dst, p)
@@ -291,8 +295,9 @@ def test_single_entry_tables_bit_exact(P):
         edges.append((3, t, pick()))
     # single-entry seeds a -> b, where b has d out-edges of probability q:
     # 6 mixed (misaligned), 20 mixed, none, 25 at 0.02 (seven groups, mostly
-    # dead), 70 at 0.01 (more than sixteen groups)
-    for a, b, d, q in ((4, 5, 6, None), (6, 7, 20, None), (8, 9, 0, None), (20, 21, 25, 0.02), (22, 23, 70, 0.01)):
+    # dead), 70 at 0.01 (more than sixteen groups), 20 certain
+    for a, b, d, q in ((4, 5, 6, None), (6, 7, 20, None), (8, 9, 0, None), (20, 21, 25, 0.02), (22, 23, 70, 0.01),
+                       (24, 25, 20, 1.0)):
         edges.append((a, b, pick()))
         for t in rng.choice(np.arange(30, n), size=d, replace=False):
             edges.append((b, int(t), pick() if q is None else q))
@@ -308,12 +313,16 @@ def test_single_entry_tables_bit_exact(P):
     keep = np.sort(keep)
     g = graph_from_edges(n, src[keep], dst[keep], p[keep])
     G = _gpu_graph(P, g)
-    for qid, S in enumerate(([0], [0, 1], [0, 1, 2], [4], [6], [8], [20], [22], [3])):
-        tab = O.stage1(g, S)
-        r = _compare(P, g, S, 40_000, qid=qid, G=G, label=f"single-entry S={S} l={tab['l']}")
-        _compare(P, g, S, 30_000, qid=qid, stream=1, first=987_654_321, G=G, label=f"single-entry S={S} X'")
-        if S != [3]:
-            assert tab["l"] == 1 and r["l"] == 1
+    for mode in (-1, 0, 1, 2):
+        P.oi_set_first_level(G.h, mode)
+        for qid, S in enumerate(([0], [0, 1], [0, 1, 2], [4], [6], [8], [20], [22], [24], [3])):
+            tab = O.stage1(g, S)
+            r = _compare(P, g, S, 40_000, qid=qid, G=G, label=f"single-entry mode {mode} S={S} l={tab['l']}")
+            _compare(P, g, S, 30_000, qid=qid, stream=1, first=987_654_321, G=G,
+                     label=f"single-entry mode {mode} S={S} X'")
+            if S != [3]:
+                assert tab["l"] == 1 and r["l"] == 1
+    P.oi_set_first_level(G.h, -1)
     a = G.estimate([0, 1], 0.1, 0.05, query_id=9)
     b = O.estimate(g, [0, 1], 0.1, 0.05, 0, 9, RUN_SEED)
     for f in ("T1", "h1", "nsigma", "D", "T", "hT"):
@@ -357,10 +366,15 @@ def test_multi_entry_first_level_bit_exact(P):
     g = graph_from_edges(n, src, dst, p)
     G = _gpu_graph(P, g)
     sets = [[u] for u in range(10)] + [[0, 1], [2, 3, 4]]
-    for qid, S in enumerate(sets):
-        tab = O.stage1(g, S)
-        _compare(P, g, S, 40_000, qid=qid, G=G, label=f"multi-entry S={S} l={tab['l']}")
-        _compare(P, g, S, 20_000, qid=qid, stream=1, first=555_555_555, G=G, label=f"multi-entry S={S} X'")
+    # the host's choice, then the general instantiation forced on every table
+    for mode in (-1, 2):
+        P.oi_set_first_level(G.h, mode)
+        for qid, S in enumerate(sets):
+            tab = O.stage1(g, S)
+            _compare(P, g, S, 40_000, qid=qid, G=G, label=f"multi-entry mode {mode} S={S} l={tab['l']}")
+            _compare(P, g, S, 20_000, qid=qid, stream=1, first=555_555_555, G=G,
+                     label=f"multi-entry mode {mode} S={S} X'")
+    P.oi_set_first_level(G.h, -1)
     # every set in one batched estimate (one launch per round over all of
     # them), replayed by the oracle set by set
     qids = np.arange(40, 40 + len(sets), dtype=np.uint32)
