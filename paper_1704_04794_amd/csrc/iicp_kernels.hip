@@ -1832,8 +1832,56 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) la
 #pragma unroll
           for (int u = 0; u < 2; ++u) d[u] = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, gg[u]);
         }
+        if constexpr (!LT && !BWD) {
+          // the claims of the two groups' live edges are issued together (the
+          // atomics are in flight at once rather than one round trip each),
+          // then the thread's new nodes take one queue reservation
+          // the live edges' targets (-1: none), selected outside any branch
+          // so that the groups' loads are waited for once, before the claims
+          int32_t tg[8];
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+          for (int u = 0; u < 2; ++u) {
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+              const uint32_t e = 4 * gg[u] + b;
+              const bool live = e >= lo_e[u] && e < hi_e[u] && edge_live(d[u].w[b], (uint32_t)pa[u][b]);
+              tg[4 * u + b] = live ? va[u][b] : -1;
+            }
+          }
+          // all eight targets are ready before the first claim (the empty asm
+          // takes them), so that no wait for the second group's loads falls
+          // between claims; the no-claim value is opaque, so that no test of
+          // a claim's result is folded into its branch (which would wait on
+          // that claim at once).  S is marked in the bitmap, so a live edge
+          // into S claims nothing
+          asm volatile("" ::"v"(tg[0]), "v"(tg[1]), "v"(tg[2]), "v"(tg[3]), "v"(tg[4]), "v"(tg[5]), "v"(tg[6]),
+                       "v"(tg[7]));
+          uint32_t none = 0xFFFFFFFFu;
+          asm volatile("" : "+v"(none));
+          uint32_t old[8];
+#pragma unroll
+          for (int k = 0; k < 8; ++k) {
+            old[k] = none;
+            if (tg[k] >= 0) old[k] = atomicOr(&bits[tg[k] >> 5], 1u << (tg[k] & 31));
+          }
+          uint32_t won = 0;
+#pragma unroll
+          for (int k = 0; k < 8; ++k)
+            if (tg[k] >= 0 && !((old[k] >> (tg[k] & 31)) & 1u)) won |= 1u << k;
+          if (won) {
+            // the tail keeps counting past the capacity, as in push
+            uint32_t pos = atomicAdd(&s_tail, (uint32_t)__popc(won));
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+              if ((won >> k) & 1u) {
+                if (pos < A.qcap) queue[pos] = tg[k];
+                ++pos;
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 2 && (LT || BWD); ++u) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const uint32_t e = 4 * gg[u] + b;
