@@ -2161,7 +2161,7 @@ oi_status oi_set_stage1_skip(oi_graph* g, int64_t min_l) {
 
 oi_status oi_set_stage1_skip_cost(oi_graph* g, double cost) {
   if (!g) return fail(OI_EINVAL, "null graph");
-  if (!(cost >= 0.0) || cost > 1e300) return fail(OI_EINVAL, "cost must be finite and non-negative");
+  if (!std::isfinite(cost) || cost < 0.0) return fail(OI_EINVAL, "cost must be finite and non-negative");
   g->skip_cost = cost;
   return OI_OK;
 }
