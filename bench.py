@@ -602,7 +602,7 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus > 1 or world > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (each GPU would run its own "
+        print("bench.py measures one GPU: the library has no multi-GPU path (each GPU would run its own "
               "samples and only per-round integer sums would be exchanged); run with --gpus 1.",
               file=sys.stderr, flush=True)
         sys.exit(2)
