@@ -1832,7 +1832,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) la
 #pragma unroll
           for (int u = 0; u < 2; ++u) d[u] = philox_draw(Q.qid, A.seed, KIND_EDGE, S.stream, s, gg[u]);
         }
-        if constexpr (!LT && !BWD) {
+        if constexpr (!LT) {
           // the claims of the two groups' live edges are issued together (the
           // atomics are in flight at once rather than one round trip each),
           // then the thread's new nodes take one queue reservation
@@ -1844,9 +1844,17 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) la
 #pragma unroll
             for (int b = 0; b < 4; ++b) {
               const uint32_t e = 4 * gg[u] + b;
-              const bool live = e >= lo_e[u] && e < hi_e[u] && edge_live(d[u].w[b], (uint32_t)pa[u][b]);
+              bool live = e >= lo_e[u] && e < hi_e[u] && edge_live(d[u].w[b], (uint32_t)pa[u][b]);
+              // the backward: an edge into S is never revealed (its target is
+              // not outside S), and a revealed one adds Y to its live sum
+              if (BWD && live) live = !(A.sbits ? seed_bit(A.sbits, va[u][b]) : in_seed_set(Q, va[u][b]));
               tg[4 * u + b] = live ? va[u][b] : -1;
             }
+          }
+          if constexpr (BWD) {
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+              if (tg[k] >= 0) atomicAdd(&A.acc_live[4 * gg[k >> 2] + (k & 3)], y);
           }
           // all eight targets are ready before the first claim (the empty asm
           // takes them), so that no wait for the second group's loads falls
@@ -1881,7 +1889,7 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) la
           }
         }
 #pragma unroll
-        for (int u = 0; u < 2 && (LT || BWD); ++u) {
+        for (int u = 0; u < 2 && LT; ++u) {
 #pragma unroll
           for (int b = 0; b < 4; ++b) {
             const uint32_t e = 4 * gg[u] + b;
@@ -2159,40 +2167,75 @@ __global__ void __launch_bounds__(256) pair_reduce_kernel(const PairSeg* ps, int
 // ---------------------------------------------------------------------------
 // backward finishing: integer Y-sums -> fp32 gradient
 // ---------------------------------------------------------------------------
+// edges per run of the finishing pass (one block per run at a time)
+constexpr int64_t kBwdRun = 2048;
+
 // Stage-2 edges: g_p = scale * (L/p - D/(1-p)), g_theta = scale * (L(1-p) - D p),
 // with D = N_u - L for an edge (u, v), v outside S (N_u: the Y-sum of the
 // samples that expand u), and L = D = 0 for an edge into S.  One thread per
-// edge; its source u is the row with row_ptr[u] <= e < row_ptr[u + 1], found
-// by binary search (the top levels of which every thread shares, so they
-// stay in cache), which keeps a hub's row spread over many threads.
+// edge, which keeps a hub's row spread over many threads; its source u is
+// the row with row_ptr[u] <= e < row_ptr[u + 1].  A block takes runs of
+// kBwdRun consecutive edges: the run's first and last sources are found by
+// two searches over all rows, and each edge then searches only between
+// them.  Every edge's gradient is written.  The live sums read are cleared,
+// so that the array is all zero again for the next backward.
 __global__ void __launch_bounds__(256) bwd_edges_kernel(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n,
-                                                        int64_t m, const float* pe_arr,
-                                                        const unsigned long long* acc_live,
+                                                        int64_t m, const float* pe_arr, unsigned long long* acc_live,
                                                         const unsigned long long* acc_node, const uint32_t* sbits,
                                                         double scale, int theta, float* grad) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m; e += stride) {
-    int64_t lo = 0, hi = n - 1;  // the first u with row_ptr[u + 1] > e
-    while (lo < hi) {
-      const int64_t mid = lo + ((hi - lo) >> 1);
-      if (row_ptr[mid + 1] > e)
-        hi = mid;
-      else
-        lo = mid + 1;
+  __shared__ int64_t s_src[2];
+  const int64_t runs = (m + kBwdRun - 1) / kBwdRun;
+  for (int64_t r = blockIdx.x; r < runs; r += gridDim.x) {
+    const int64_t first = r * kBwdRun;
+    const int64_t last = (first + kBwdRun < m ? first + kBwdRun : m) - 1;
+    if (threadIdx.x < 2) {
+      // the source of the run's first (thread 0) and last (thread 1) edge:
+      // the first u with row_ptr[u + 1] > e
+      const int64_t e = threadIdx.x ? last : first;
+      int64_t lo = 0, hi = n - 1;
+      while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (row_ptr[mid + 1] > e)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      s_src[threadIdx.x] = lo;
     }
-    const double p = (double)pe_arr[e];
-    const unsigned long long L = acc_live[e];
-    const unsigned long long D = seed_bit(sbits, eg[e >> 2].v[e & 3]) ? 0ull : acc_node[lo] - L;
-    double g = 0.0;
-    if (theta) {
-      g = scale * ((double)L * (1.0 - p) - (double)D * p);
-    } else {
-      double a = 0.0, b = 0.0;
-      if (L) a = (double)L / p;
-      if (D) b = (double)D / (1.0 - p);
-      g = scale * (a - b);
+    __syncthreads();
+    const int64_t u0 = s_src[0], u1 = s_src[1];
+    for (int64_t e = first + threadIdx.x; e <= last; e += blockDim.x) {
+      int64_t lo = u0, hi = u1;  // e's source lies between the run's first and last
+      while (lo < hi) {
+        const int64_t mid = lo + ((hi - lo) >> 1);
+        if (row_ptr[mid + 1] > e)
+          hi = mid;
+        else
+          lo = mid + 1;
+      }
+      const unsigned long long N = acc_node[lo];
+      double g = 0.0;
+      if (N == 0) {
+        // no sample expanded the source: L = D = 0 (a live sum only grows
+        // with its source's expansion sum)
+        g = scale * 0.0;
+      } else {
+        const double p = (double)pe_arr[e];
+        const unsigned long long L = acc_live[e];
+        if (L) acc_live[e] = 0ull;  // left cleared for the next backward
+        const unsigned long long D = seed_bit(sbits, eg[e >> 2].v[e & 3]) ? 0ull : N - L;
+        if (theta) {
+          g = scale * ((double)L * (1.0 - p) - (double)D * p);
+        } else {
+          double a = 0.0, b = 0.0;
+          if (L) a = (double)L / p;
+          if (D) b = (double)D / (1.0 - p);
+          g = scale * (a - b);
+        }
+      }
+      grad[e] = (float)g;
     }
-    grad[e] = (float)g;
+    __syncthreads();  // s_src is rewritten by the next run
   }
 }
 
@@ -2539,10 +2582,10 @@ hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float
 }
 
 hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
-                            const unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
+                            unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
                             double scale, int theta, float* grad, hipStream_t st) {
   if (m == 0) return hipSuccess;
-  int64_t blocks = (m + 255) / 256;
+  int64_t blocks = (m + kBwdRun - 1) / kBwdRun;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row_ptr, eg, n, m, pe, L, N, sbits,
                      scale, theta, grad);

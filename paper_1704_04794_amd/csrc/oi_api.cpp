@@ -48,7 +48,7 @@ hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, cons
 hipError_t launch_coin_probe(uint64_t samples, uint32_t groups_per_sample, uint32_t seed, uint32_t qid,
                              unsigned long long* out, int cus, hipStream_t st);
 hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
-                            const unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
+                            unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
                             double scale, int theta, float* grad, hipStream_t st);
 hipError_t launch_bwd_stage1(const float* pe, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
                              const unsigned long long* acc_tab, unsigned long long sumY, double scale, int theta,
@@ -206,6 +206,7 @@ struct oi_graph {
   // backward workspaces, kept between calls (the per-edge and per-node sums
   // are 8 B each: allocating them per call cost more than clearing them)
   DevBuf d_bacc, d_btab, d_bseoff, d_bse, d_bP, d_bsbits;
+  bool bacc_live_zero = false;  // the backward's per-edge live sums are all zero
   int large_blocks = 0;
   uint32_t large_qcap = 0;          // queue entries per large-kernel block
   DevBuf d_gbits, d_gqueue;         // full-size pool for samples that outgrow large_qcap
@@ -1954,8 +1955,8 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
   HostQuery Q;
   Q.qid = query_id;
   OI_TRY(build_table(g, seeds, k, Q));
-  HIP_TRY(hipMemsetAsync(grad_out, 0, (size_t)g->m * 4, g->stream));
   if (Q.beta0 == 0.0) {
+    HIP_TRY(hipMemsetAsync(grad_out, 0, (size_t)g->m * 4, g->stream));
     HIP_TRY(hipStreamSynchronize(g->stream));
     return OI_OK;
   }
@@ -1977,10 +1978,20 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
   DevBuf& se = g->d_bse;
   DevBuf& P = g->d_bP;
   // per edge the live Y-sum, then per node the Y-sum of the samples that expand it
-  const size_t acc_words = (size_t)std::max<int64_t>(g->m, 1) + (size_t)std::max<int64_t>(g->n, 1);
+  // (the finishing pass writes every edge's gradient and clears the live
+  // sums it reads, so after a completed backward only the node sums need
+  // clearing; a new buffer or an unfinished backward clears everything)
+  const size_t live_words = (size_t)std::max<int64_t>(g->m, 1);
+  const size_t acc_words = live_words + (size_t)std::max<int64_t>(g->n, 1);
+  const void* acc_before = acc.p;
   HIP_TRY(acc.ensure(acc_words * 8));
+  if (acc.p != acc_before) g->bacc_live_zero = false;
   HIP_TRY(tab.ensure((size_t)std::max<int64_t>(Q.l, 1) * 8));
-  HIP_TRY(hipMemsetAsync(acc.p, 0, acc_words * 8, g->stream));
+  if (g->bacc_live_zero)
+    HIP_TRY(hipMemsetAsync(acc.as<unsigned long long>() + live_words, 0, (acc_words - live_words) * 8, g->stream));
+  else
+    HIP_TRY(hipMemsetAsync(acc.p, 0, acc_words * 8, g->stream));
+  g->bacc_live_zero = false;
   HIP_TRY(hipMemsetAsync(tab.p, 0, (size_t)std::max<int64_t>(Q.l, 1) * 8, g->stream));
   // S as an n-bit bitmap, so that the backward's test of every revealed
   // edge for a target in S is one load
@@ -2011,6 +2022,7 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
   }
   HIP_TRY(oi::launch_bwd_edges(g->d_row_ptr.as<int64_t>(), g->d_eg.as<oi::EdgeGroup>(), g->n, g->m,
                                g->d_p.as<float>(), bb.live, bb.node, bb.sbits, scale, theta, grad_out, g->stream));
+  g->bacc_live_zero = true;
   HIP_TRY(seoff.ensure(Q.se_off.size() * 8));
   HIP_TRY(se.ensure(std::max<size_t>(Q.se.size(), 1) * 8));
   HIP_TRY(P.ensure(std::max<size_t>(Q.P.size(), 1) * 8));

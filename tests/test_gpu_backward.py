@@ -68,6 +68,31 @@ def test_tiny16_matches_oracle_and_enumeration(P):
     G.close()
 
 
+def test_repeated_backwards_on_one_graph(P):
+    """The finishing pass clears the per-edge live sums it reads, and the
+    next backward on the same graph starts from them: backwards for seed
+    sets A, B, A in a row give A's gradient bit for bit twice, and every
+    one equals the fp64 oracle edge by edge (samples large enough to reach
+    the large-cascade kernel included)."""
+    import torch
+    c = chung_lu_graph(20000, 200000, 2.1, 7)
+    c = c.with_p(wc_probs(c))
+    G = P.Graph.from_inputs(c)
+    A = uniform_seed_set(c, 3, 21)
+    B = uniform_seed_set(c, 40, 22)
+    N = 30_000
+    out = []
+    for S, qid in ((A, 1), (B, 2), (A, 1)):
+        print(f"[gpu] repeated backward |S|={len(S)} N={N} qid={qid}", flush=True)
+        g = torch.empty(G.m, dtype=torch.float32, device="cuda")
+        G.backward(S, N, g, query_id=qid)
+        out.append(g.cpu().numpy())
+        ref, _ = _oracle_grad(c, S, N, qid=qid)
+        _per_edge(out[-1].astype(np.float64), ref)
+    assert np.array_equal(out[0].view(np.uint32), out[2].view(np.uint32))
+    G.close()
+
+
 def test_theta_parameterisation(P):
     import torch
     g = tiny16_graph()
