@@ -1888,34 +1888,23 @@ __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(8))) la
             }
           }
         }
+        if constexpr (LT) {
 #pragma unroll
-        for (int u = 0; u < 2 && LT; ++u) {
+          for (int u = 0; u < 2; ++u) {
 #pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const uint32_t e = 4 * gg[u] + b;
-            if (LT && e >= lo_e[u] && e < hi_e[u]) {
-              // the LT model: v activates through e iff v's choice word
-              // falls in e's interval (S is marked, so an edge into S and a
-              // node already active draw nothing)
-              const int32_t v = va[u][b];
-              if (!((gptr(bits)[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u)) {
-                const Words dv = philox_draw(Q.qid, A.seed, KIND_LT, S.stream, s, (uint64_t)((uint32_t)v >> 2));
-                const uint32_t W = word_at(dv, v & 3);
-                const OI_GLOBAL LtEdge* iv = gptr(A.lt_iv) + e;
-                if (W >= iv->lo && W <= iv->last && claim(bits, v)) push(queue, &s_tail, A.qcap, v);
-              }
-            } else if (!LT && e >= lo_e[u] && e < hi_e[u]) {
-              const bool live = edge_live(d[u].w[b], (uint32_t)pa[u][b]);
-              const int32_t v = va[u][b];
-              if (BWD) {
-                // an edge into S is never revealed (its target is not outside S)
-                if (live && !(A.sbits ? seed_bit(A.sbits, v) : in_seed_set(Q, v))) {
-                  atomicAdd(&A.acc_live[e], y);
-                  if (claim(bits, v)) push(queue, &s_tail, A.qcap, v);
+            for (int b = 0; b < 4; ++b) {
+              const uint32_t e = 4 * gg[u] + b;
+              if (e >= lo_e[u] && e < hi_e[u]) {
+                // the LT model: v activates through e iff v's choice word
+                // falls in e's interval (S is marked, so an edge into S and a
+                // node already active draw nothing)
+                const int32_t v = va[u][b];
+                if (!((gptr(bits)[(uint32_t)v >> 5] >> ((uint32_t)v & 31u)) & 1u)) {
+                  const Words dv = philox_draw(Q.qid, A.seed, KIND_LT, S.stream, s, (uint64_t)((uint32_t)v >> 2));
+                  const uint32_t W = word_at(dv, v & 3);
+                  const OI_GLOBAL LtEdge* iv = gptr(A.lt_iv) + e;
+                  if (W >= iv->lo && W <= iv->last && claim(bits, v)) push(queue, &s_tail, A.qcap, v);
                 }
-              } else if (live && claim(bits, v)) {
-                // S is marked in the bitmap, so a live edge into S claims nothing
-                push(queue, &s_tail, A.qcap, v);
               }
             }
           }
