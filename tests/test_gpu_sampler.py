@@ -385,3 +385,18 @@ def test_multi_entry_first_level_bit_exact(P):
             assert a[f] == b["rsa"][f], (S, f, a[f], b["rsa"][f])
         assert a["oi"] == b["oi"], S
     G.close()
+
+
+def test_first_level_mode_validation(P):
+    """oi_set_first_level takes -1, 0, 1 or 2."""
+    g = fig1_graph()
+    G = _gpu_graph(P, g)
+    try:
+        for bad in (-2, 3):
+            with pytest.raises(P.OiError) as ei:
+                P.oi_set_first_level(G.h, bad)
+            assert ei.value.status == P._binding.OI_EINVAL
+        for ok in (-1, 0, 1, 2):
+            P.oi_set_first_level(G.h, ok)
+    finally:
+        G.close()

@@ -128,3 +128,18 @@ def test_density_test_agrees_with_the_oracle(P, p):
         assert r["l"] == 4096
     finally:
         G.close()
+
+
+def test_density_cost_validation(P):
+    """oi_set_stage1_skip_cost takes a finite, non-negative ratio."""
+    g = star_graph(np.full(8, 0.1, np.float32))
+    G = P.Graph.from_inputs(g)
+    try:
+        for bad in (-1.0, float("nan"), float("inf")):
+            with pytest.raises(P.OiError) as ei:
+                P.oi_set_stage1_skip_cost(G.h, bad)
+            assert ei.value.status == P._binding.OI_EINVAL
+        P.oi_set_stage1_skip_cost(G.h, 0.0)
+        P.oi_set_stage1_skip_cost(G.h, 8.0)
+    finally:
+        G.close()
