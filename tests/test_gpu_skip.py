@@ -115,13 +115,20 @@ def test_skip_noalloc_matches(P, skip65):
     G.close()
 
 
-@pytest.mark.parametrize("p", [0.027, 0.0275])
+@pytest.mark.parametrize("p", [0.027, 0.0275, "mixed"])
 def test_density_test_agrees_with_the_oracle(P, p):
     """Stars of 4096 leaves with every P_j = p, at the default settings
     (tables from 4096 entries, cost 8): the density test skip-samples the
-    first (8 W = 8 (16 + 4096 p) = 1013 <= 1024) and not the second (1029);
-    both sides take the same decision, so the samples agree bit for bit."""
-    g = star_graph(np.full(4096, p, np.float32))
+    first (8 W = 8 (16 + 4096 p) = 1013 <= 1024) and not the second (1029),
+    and skip-samples a star of 2048 heavy (0.9) and 2048 light (0.02)
+    leaves, whose heavy entries do not count; both sides take the same
+    decision, so the samples agree bit for bit."""
+    if p == "mixed":
+        q = np.full(4096, 0.02, np.float32)
+        q[::2] = 0.9
+    else:
+        q = np.full(4096, p, np.float32)
+    g = star_graph(q)
     G = P.Graph.from_inputs(g)
     try:
         r, _ = _compare(G, g, [0], 1 << 14, qid=11, label=f"density test p={p}")

@@ -149,18 +149,33 @@ def _walk_draws(P):
     return W
 
 
-@pytest.mark.parametrize("p, skipped", [(0.002, True), (0.027, True), (0.0275, False), (0.2, False)])
+def _star_probs_of(p):
+    """Leaf probabilities: every leaf p, or (for p = "mixed") 2048 heavy
+    leaves at 0.9 interleaved with 2048 light ones at 0.02."""
+    if p == "mixed":
+        q = np.full(4096, 0.02, np.float32)
+        q[::2] = 0.9
+        return q
+    return np.full(4096, p, np.float32)
+
+
+@pytest.mark.parametrize("p, skipped", [(0.002, True), (0.027, True), (0.0275, False), (0.2, False),
+                                        ("mixed", True)])
 def test_density_test_decides_by_the_expected_draws(p, skipped):
     """A star of 4096 leaves with every P_j = p: W = 16 + 4096 p walk draws
     against 1024 coin blocks, so with the default cost 8 the table is
     skip-sampled iff p <= 0.02734375.  Its samples are then those drawn with
     the density test off (cost 0), else those of the plain coins (skip
-    sampling off); the two differ."""
-    g = star_graph(np.full(4096, p, np.float32))
+    sampling off); the two differ.  Heavy entries (P >= 1/2) keep their
+    coins and do not count: half the leaves at 0.9 and half at 0.02 give
+    W = 16 + 2048 * 0.02, skip-sampled (counting the heavy ones would not
+    be)."""
+    g = star_graph(_star_probs_of(p))
     t = O.stage1(g, [0])
     assert t["l"] == 4096
     W = _walk_draws(t["P"])
-    assert abs(W - (16 + 4096 * p)) < 1e-3 * W
+    closed = 16 + 2048 * 0.02 if p == "mixed" else 16 + 4096 * p
+    assert abs(W - closed) < 1e-3 * W
     assert (W * 8.0 <= 4096 / 4.0) == skipped
     N = 4000
     d = O.sample_fixed(g, [0], 5, SEED, 0, 0, N, want_e=True)
