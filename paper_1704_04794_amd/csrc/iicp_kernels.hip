@@ -2156,48 +2156,62 @@ __global__ void __launch_bounds__(256) pair_reduce_kernel(const PairSeg* ps, int
 // ---------------------------------------------------------------------------
 // backward finishing: integer Y-sums -> fp32 gradient
 // ---------------------------------------------------------------------------
-// edges per run of the finishing pass (one block per run at a time)
+// edges per run of the finishing pass (one block per run at a time), and
+// the longest slice of row_ptr a run stages in LDS
 constexpr int64_t kBwdRun = 2048;
+constexpr int64_t kBwdRows = 2048;
+
+// src[r] = the source of run r's first edge (r < runs), src[runs] = the
+// source of the last edge: the first u with row_ptr[u + 1] > e, one search
+// per thread
+__global__ void __launch_bounds__(256) bwd_run_sources_kernel(const int64_t* row_ptr, int64_t n, int64_t m,
+                                                              int64_t runs, int64_t* src) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r <= runs; r += stride) {
+    const int64_t e = r < runs ? r * kBwdRun : m - 1;
+    int64_t lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (row_ptr[mid + 1] > e)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    src[r] = lo;
+  }
+}
 
 // Stage-2 edges: g_p = scale * (L/p - D/(1-p)), g_theta = scale * (L(1-p) - D p),
 // with D = N_u - L for an edge (u, v), v outside S (N_u: the Y-sum of the
 // samples that expand u), and L = D = 0 for an edge into S.  One thread per
 // edge, which keeps a hub's row spread over many threads; its source u is
 // the row with row_ptr[u] <= e < row_ptr[u + 1].  A block takes runs of
-// kBwdRun consecutive edges: the run's first and last sources are found by
-// two searches over all rows, and each edge then searches only between
-// them.  Every edge's gradient is written.  The live sums read are cleared,
-// so that the array is all zero again for the next backward.
+// kBwdRun consecutive edges: run r's sources lie in [src[r], src[r + 1]],
+// whose slice of row_ptr is staged in LDS when it fits (else the search
+// reads row_ptr itself).  Every edge's gradient is written.  The live sums
+// read are cleared, so that the array is all zero again for the next
+// backward.
 __global__ void __launch_bounds__(256) bwd_edges_kernel(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n,
                                                         int64_t m, const float* pe_arr, unsigned long long* acc_live,
                                                         const unsigned long long* acc_node, const uint32_t* sbits,
-                                                        double scale, int theta, float* grad) {
-  __shared__ int64_t s_src[2];
+                                                        const int64_t* src, double scale, int theta, float* grad) {
+  __shared__ int64_t s_rp[kBwdRows + 1];
   const int64_t runs = (m + kBwdRun - 1) / kBwdRun;
   for (int64_t r = blockIdx.x; r < runs; r += gridDim.x) {
     const int64_t first = r * kBwdRun;
     const int64_t last = (first + kBwdRun < m ? first + kBwdRun : m) - 1;
-    if (threadIdx.x < 2) {
-      // the source of the run's first (thread 0) and last (thread 1) edge:
-      // the first u with row_ptr[u + 1] > e
-      const int64_t e = threadIdx.x ? last : first;
-      int64_t lo = 0, hi = n - 1;
-      while (lo < hi) {
-        const int64_t mid = lo + ((hi - lo) >> 1);
-        if (row_ptr[mid + 1] > e)
-          hi = mid;
-        else
-          lo = mid + 1;
-      }
-      s_src[threadIdx.x] = lo;
-    }
+    const int64_t u0 = src[r], u1 = src[r + 1];
+    // row_ptr[u0 + 1 .. u1 + 1]: the bounds the search compares against
+    const int64_t nr = u1 - u0 + 1;
+    const bool staged = nr <= kBwdRows + 1;
+    if (staged)
+      for (int64_t x = threadIdx.x; x < nr; x += blockDim.x) s_rp[x] = row_ptr[u0 + 1 + x];
     __syncthreads();
-    const int64_t u0 = s_src[0], u1 = s_src[1];
     for (int64_t e = first + threadIdx.x; e <= last; e += blockDim.x) {
-      int64_t lo = u0, hi = u1;  // e's source lies between the run's first and last
+      int64_t lo = u0, hi = u1;  // e's source lies between src[r] and src[r + 1]
       while (lo < hi) {
         const int64_t mid = lo + ((hi - lo) >> 1);
-        if (row_ptr[mid + 1] > e)
+        if ((staged ? s_rp[mid - u0] : row_ptr[mid + 1]) > e)
           hi = mid;
         else
           lo = mid + 1;
@@ -2224,7 +2238,7 @@ __global__ void __launch_bounds__(256) bwd_edges_kernel(const int64_t* row_ptr, 
       }
       grad[e] = (float)g;
     }
-    __syncthreads();  // s_src is rewritten by the next run
+    __syncthreads();  // s_rp is rewritten by the next run
   }
 }
 
@@ -2570,14 +2584,23 @@ hipError_t launch_theta_to_p(const float* theta, int64_t m, EdgeGroup* eg, float
   return hipGetLastError();
 }
 
+size_t bwd_run_count(int64_t m) { return m > 0 ? (size_t)((m + kBwdRun - 1) / kBwdRun) : 0; }
+
+// src: bwd_run_count(m) + 1 entries of workspace
 hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
                             unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
-                            double scale, int theta, float* grad, hipStream_t st) {
+                            int64_t* src, double scale, int theta, float* grad, hipStream_t st) {
   if (m == 0) return hipSuccess;
-  int64_t blocks = (m + kBwdRun - 1) / kBwdRun;
+  const int64_t runs = (int64_t)bwd_run_count(m);
+  int64_t sb = (runs + 1 + 255) / 256;
+  if (sb > 65536) sb = 65536;
+  hipLaunchKernelGGL(bwd_run_sources_kernel, dim3((unsigned)sb), dim3(256), 0, st, row_ptr, n, m, runs, src);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t blocks = runs;
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(bwd_edges_kernel, dim3((unsigned)blocks), dim3(256), 0, st, row_ptr, eg, n, m, pe, L, N, sbits,
-                     scale, theta, grad);
+                     src, scale, theta, grad);
   return hipGetLastError();
 }
 

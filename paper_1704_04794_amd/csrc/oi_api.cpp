@@ -47,9 +47,10 @@ hipError_t launch_gather_probe(const int64_t* row_ptr, const EdgeGroup* eg, cons
                                unsigned long long* out, int cus, hipStream_t st);
 hipError_t launch_coin_probe(uint64_t samples, uint32_t groups_per_sample, uint32_t seed, uint32_t qid,
                              unsigned long long* out, int cus, hipStream_t st);
+size_t bwd_run_count(int64_t m);
 hipError_t launch_bwd_edges(const int64_t* row_ptr, const EdgeGroup* eg, int64_t n, int64_t m, const float* pe,
                             unsigned long long* L, const unsigned long long* N, const uint32_t* sbits,
-                            double scale, int theta, float* grad, hipStream_t st);
+                            int64_t* src, double scale, int theta, float* grad, hipStream_t st);
 hipError_t launch_bwd_stage1(const float* pe, const int64_t* se_off, const int64_t* se, const double* P, int64_t l,
                              const unsigned long long* acc_tab, unsigned long long sumY, double scale, int theta,
                              float* grad, hipStream_t st);
@@ -205,7 +206,7 @@ struct oi_graph {
   DevBuf d_y, d_def, d_def2, d_ctl, d_segs, d_qs, d_sums, d_bits, d_queue;
   // backward workspaces, kept between calls (the per-edge and per-node sums
   // are 8 B each: allocating them per call cost more than clearing them)
-  DevBuf d_bacc, d_btab, d_bseoff, d_bse, d_bP, d_bsbits;
+  DevBuf d_bacc, d_btab, d_bseoff, d_bse, d_bP, d_bsbits, d_brun;
   bool bacc_live_zero = false;  // the backward's per-edge live sums are all zero
   int large_blocks = 0;
   uint32_t large_qcap = 0;          // queue entries per large-kernel block
@@ -2020,8 +2021,10 @@ oi_status oi_backward(oi_graph* g, uint32_t query_id, const int32_t* seeds, int6
     if (g->m) HIP_TRY(hipMemcpy(g->d_p.p, g->p.data(), (size_t)g->m * sizeof(float), hipMemcpyHostToDevice));
     g->d_p_ok = true;
   }
+  HIP_TRY(g->d_brun.ensure((oi::bwd_run_count(g->m) + 1) * sizeof(int64_t)));
   HIP_TRY(oi::launch_bwd_edges(g->d_row_ptr.as<int64_t>(), g->d_eg.as<oi::EdgeGroup>(), g->n, g->m,
-                               g->d_p.as<float>(), bb.live, bb.node, bb.sbits, scale, theta, grad_out, g->stream));
+                               g->d_p.as<float>(), bb.live, bb.node, bb.sbits, g->d_brun.as<int64_t>(), scale, theta,
+                               grad_out, g->stream));
   g->bacc_live_zero = true;
   HIP_TRY(seoff.ensure(Q.se_off.size() * 8));
   HIP_TRY(se.ensure(std::max<size_t>(Q.se.size(), 1) * 8));
